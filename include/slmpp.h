@@ -1,0 +1,222 @@
+/*
+ * slmpp.h -- C-ABI of the MI355X (gfx950) SL-MPP5/7 Vlasov sweep library.
+ *
+ * The library advances a phase-space distribution f(x, v) of dimension
+ * D = 1, 2 or 3 (a DdDv grid) with the directionally split, conservative
+ * semi-Lagrangian scheme of Tanaka, Yoshikawa, Minoshima & Yoshida
+ * (arXiv:1702.08521): each one-dimensional sweep builds the CSL flux
+ * polynomial (Sec. 2.1.2), applies the monotonicity-preserving constraint
+ * (App. A) and the positivity-preserving flux limiter (Sec. 2.1.1), and
+ * updates the cell averages in conservative form (Eq. (SL)).  Departure
+ * offsets larger than one cell are split into an integer cell shift and a
+ * fractional flux.  Around the sweeps sit the velocity moment, the periodic
+ * Poisson solve with the 2nd/4th/6th-order Green functions and finite-
+ * difference forces (Sec. 2.2, App. C), and the Strang step of
+ * Eq. (splitting).
+ *
+ * Conventions
+ *  - All pointers named *_dev are device pointers on the current HIP
+ *    device; *_host are host pointers.  The caller owns every buffer it
+ *    passes in; the library never frees them.
+ *  - f is stored row-major as f[x1]..[xD][v1]..[vD] (vD fastest), in the
+ *    storage type of the grid (double or float), prod(nx)*prod(nv) values.
+ *  - Spatial fields (rho, phi, one acceleration component) are double
+ *    arrays of prod(nx) values, row-major [x1]..[xD].  An acceleration
+ *    array "accel" holds D such components back to back (component l at
+ *    offset l*prod(nx)).
+ *  - Every call that enqueues work does so on the stream given at create,
+ *    asynchronously, and returns once the work is enqueued; the calls that
+ *    copy to the host (slmpp_get_f, slmpp_diag, slmpp_timing_read,
+ *    slmpp_sync) synchronise that stream.
+ *  - Arguments are validated on the host before anything is enqueued.  A
+ *    failing call returns a non-zero slmpp_status, enqueues nothing and
+ *    leaves f unchanged; slmpp_last_error() returns a message.  A fault of
+ *    earlier asynchronous work is reported as SLMPP_ERR_DEVICE by the next
+ *    synchronising call.
+ *  - Calls on one context must not run concurrently from several host
+ *    threads.
+ */
+#ifndef SLMPP_H
+#define SLMPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLMPP_ABI_VERSION 1
+
+typedef enum {
+  SLMPP_OK = 0,
+  SLMPP_ERR_INVALID = 1,   /* bad argument (null pointer, dim out of range, enum value) */
+  SLMPP_ERR_SHAPE = 2,     /* inconsistent or oversized grid / array size           */
+  SLMPP_ERR_NONFINITE = 3, /* non-finite time step or grid bound                   */
+  SLMPP_ERR_WORKSPACE = 4, /* workspace smaller than slmpp_workspace_bytes()       */
+  SLMPP_ERR_DEVICE = 5,    /* a HIP call failed                                    */
+  SLMPP_ERR_STATE = 6      /* call not valid in the current state                  */
+} slmpp_status;
+
+typedef enum { SLMPP_F64 = 0, SLMPP_F32 = 1 } slmpp_dtype;
+
+/* Boundary condition of an axis.  OUTFLOW reads zero outside the domain,
+ * so nothing flows in and what crosses the edge leaves the grid. */
+typedef enum { SLMPP_BC_PERIODIC = 0, SLMPP_BC_OUTFLOW = 1 } slmpp_bc;
+
+/* Interface flux of a sweep: the CSL polynomial alone, with the MP
+ * constraint (SL-MP5/7), or with the MP constraint and the PP limiter
+ * (SL-MPP5/7, the paper's production scheme). */
+typedef enum { SLMPP_LIM_NONE = 0, SLMPP_LIM_MP = 1, SLMPP_LIM_MPP = 2 } slmpp_limiter;
+
+/* Grid and scheme description.  Entries beyond D are ignored. */
+typedef struct {
+  int32_t D;             /* spatial dimensions = velocity dimensions, 1..3   */
+  int32_t order;         /* 5 (CSL5 / MP5) or 7 (CSL7 / MP7)                  */
+  int32_t limiter;       /* slmpp_limiter                                     */
+  int32_t poisson_order; /* 2, 4 or 6: Green function and FDA order (App. C)  */
+  int64_t nx[3];         /* cells per spatial axis, 1..65536                  */
+  int64_t nv[3];         /* cells per velocity axis, 1..65536                 */
+  double x_lo[3], x_hi[3]; /* spatial domain, cell centres at lo+(i+1/2)dx    */
+  double v_lo[3], v_hi[3]; /* velocity domain                                 */
+  double alpha;          /* MP parameter (App. A: alpha = 4), > 0             */
+  double kappa;          /* Poisson coupling: lap(phi) = kappa (rho - mean);
+                            4 pi G for gravity, -1 for electrons with a
+                            neutralising ion background (omega_pe = 1)      */
+  int32_t x_bc, v_bc;    /* slmpp_bc of the spatial / velocity axes; the
+                            field solve is periodic in space                */
+  int32_t storage;       /* slmpp_dtype of f (sweeps compute in this type;
+                            moment, Poisson and forces are always double)   */
+  int32_t flags;         /* must be 0                                        */
+} slmpp_grid_desc;
+
+typedef struct slmpp_ctx slmpp_ctx;
+
+/* Diagnostics of the current state (Sec. 3: mass, energy, mode amplitude). */
+typedef struct {
+  double mass;          /* sum f * dx^D dv^D (double, compensated)            */
+  double f_min, f_max;  /* extreme cell values of f                            */
+  double field_energy;  /* 1/2 sum |a|^2 dx^D of the context's acceleration    */
+  double mode_amp;      /* |sum_x a_1(x) exp(-2 pi i x1 / L1)| / prod(nx)     */
+  int64_t nonfinite;    /* number of non-finite values of f                    */
+} slmpp_diag_out;
+
+/* Per-kernel-class timing gathered with HIP events on the context stream. */
+#define SLMPP_TIMING_CLASSES 4 /* 0: sweeps along a strided axis,
+                                  1: sweeps along the contiguous axis,
+                                  2: velocity moment, 3: Poisson + force   */
+typedef struct {
+  int64_t launches[SLMPP_TIMING_CLASSES];
+  double total_ms[SLMPP_TIMING_CLASSES];  /* summed kernel durations       */
+  double bytes[SLMPP_TIMING_CLASSES];     /* algorithmic HBM bytes summed  */
+  double cells[SLMPP_TIMING_CLASSES];     /* cell updates (sweeps) summed  */
+} slmpp_timing;
+
+/* ABI version compiled into the library (SLMPP_ABI_VERSION). */
+int32_t slmpp_abi_version(void);
+
+/* Device bytes of the workspace a context over `desc` needs (rho, phi,
+ * forces, Green table, Fourier buffers, reduction scratch, init staging).
+ * Returns 0 when desc is invalid. */
+size_t slmpp_workspace_bytes(const slmpp_grid_desc* desc);
+
+/* Check desc without touching the device.  Returns SLMPP_OK or the code
+ * create would return; msg (may be NULL) receives the reason. */
+slmpp_status slmpp_validate(const slmpp_grid_desc* desc, char* msg, size_t msg_len);
+
+/* Create a context.  f_dev: caller-owned device array of the grid's cells
+ * in the storage type; it must stay allocated and unmoved until destroy.
+ * work_dev/work_bytes: caller-owned device workspace of at least
+ * slmpp_workspace_bytes(desc) bytes, 256-byte aligned.  hip_stream: the
+ * hipStream_t all work is enqueued on (NULL = the null stream).  On
+ * success *out receives the context; f is not touched. */
+slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_dev,
+                          size_t work_bytes, void* hip_stream, slmpp_ctx** out);
+
+/* Release the context's own host state (never the caller's buffers). */
+slmpp_status slmpp_destroy(slmpp_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none); with ctx == NULL,
+ * the message of the last failing slmpp_create/validate in this thread. */
+const char* slmpp_last_error(const slmpp_ctx* ctx);
+
+/* f <- f_host (n = number of cells, double values, converted to the
+ * storage type).  Blocking copy. */
+slmpp_status slmpp_init_f_host(slmpp_ctx* ctx, const double* f_host, int64_t n);
+
+/* f(x, v) <- s(x) * g1(v1) * g2(v2) * g3(v3), the product taken left to
+ * right in double and rounded once to the storage type.  s_host has
+ * prod(nx) values, g_l has nv_l values (NULL for l >= D).  The factors are
+ * staged through the workspace. */
+slmpp_status slmpp_init_f_separable(slmpp_ctx* ctx, const double* s_host, const double* g1,
+                                    const double* g2, const double* g3);
+
+/* One SL step of every pencil along x_dim (dim = 0..D-1) with speed
+ * v_dim = the velocity cell centre of the pencil and time step dt
+ * (Eq. (adv_pos)).  In place.  dt may be negative (time reversal). */
+slmpp_status slmpp_advect_x(slmpp_ctx* ctx, int32_t dim, double dt);
+
+/* One SL step of every pencil along v_dim with speed accel_dev[ix] (the
+ * acceleration component at the pencil's spatial cell, prod(nx) doubles on
+ * the device), Eq. (adv_vel).  In place. */
+slmpp_status slmpp_advect_v(slmpp_ctx* ctx, int32_t dim, double dt, const double* accel_dev);
+
+/* rho_dev[ix] <- dv^D * sum_v f(ix, v) (compensated double accumulation). */
+slmpp_status slmpp_density_moment(slmpp_ctx* ctx, double* rho_dev);
+
+/* Periodic Poisson solve lap(phi) = kappa (rho - mean rho) by discrete
+ * Fourier transform with the Green function of order poisson_order
+ * (Sec. 2.2), then accel_l = -d(phi)/dx_l by the FDA of the same order
+ * (App. C).  phi_dev may be NULL.  rho_dev and accel_dev (D*prod(nx)) are
+ * device arrays that must not overlap the workspace. */
+slmpp_status slmpp_poisson_solve(slmpp_ctx* ctx, const double* rho_dev, double* phi_dev,
+                                 double* accel_dev);
+
+/* Recompute the context's own acceleration from the current f
+ * (density moment + Poisson solve). */
+slmpp_status slmpp_field(slmpp_ctx* ctx);
+
+/* Device pointers of the context's rho, phi and accel arrays (read-only
+ * for the caller; valid until destroy).  Any output pointer may be NULL. */
+slmpp_status slmpp_field_ptrs(const slmpp_ctx* ctx, const double** rho_dev,
+                              const double** phi_dev, const double** accel_dev);
+
+/* Copy the context's rho (prod(nx)) and acceleration (D*prod(nx)) to the
+ * host as of the last field computation; either pointer may be NULL.
+ * Synchronises. */
+slmpp_status slmpp_get_field(slmpp_ctx* ctx, double* rho_host, double* accel_host);
+
+/* One time step of Eq. (splitting): v1..vD with dt/2 using the context's
+ * acceleration, xD..x1 with dt, density moment + Poisson, v1..vD with
+ * dt/2 using the new acceleration.  If f was changed by any other call
+ * since the acceleration was last computed, the acceleration is first
+ * recomputed from f.  nsteps >= 1 steps are enqueued back to back. */
+slmpp_status slmpp_step(slmpp_ctx* ctx, double dt, int32_t nsteps);
+
+/* Copy f to the host as doubles (n = number of cells).  Synchronises. */
+slmpp_status slmpp_get_f(slmpp_ctx* ctx, double* f_host, int64_t n);
+
+/* Diagnostics of f and of the context's acceleration.  Synchronises. */
+slmpp_status slmpp_diag(slmpp_ctx* ctx, slmpp_diag_out* out);
+
+/* Wait for all work enqueued on the context's stream. */
+slmpp_status slmpp_sync(slmpp_ctx* ctx);
+
+/* Enable (1) or disable (0) per-launch HIP-event timing of the context's
+ * kernels, and clear the accumulated figures. */
+slmpp_status slmpp_timing_enable(slmpp_ctx* ctx, int32_t on);
+
+/* Read the accumulated timing (synchronises). */
+slmpp_status slmpp_timing_read(slmpp_ctx* ctx, slmpp_timing* out);
+
+/* Plain device copy of `bytes` bytes by a streaming kernel (16-byte
+ * vectors; both pointers 16-byte aligned, no overlap) on hip_stream.  A
+ * reference of known traffic for hardware counters. */
+slmpp_status slmpp_copy_device(void* dst_dev, const void* src_dev, size_t bytes,
+                               void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLMPP_H */

@@ -1,0 +1,677 @@
+// Host runtime behind the C-ABI of include/slmpp.h: argument validation,
+// workspace layout, launch plans, the Strang step and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "slmpp_internal.hpp"
+
+using namespace slmpp;
+
+namespace {
+
+constexpr int64_t kMaxAxis = 4096;               // LDS holds a whole pencil
+constexpr int64_t kMaxCells = (int64_t)1 << 40;  // 1.1e12 cells
+constexpr int64_t kStageChunk = (int64_t)1 << 22;  // doubles per host<->device chunk
+
+thread_local std::string g_error;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, stage, total;
+  int64_t stage_doubles;
+};
+
+int64_t n_space(const slmpp_grid_desc& d) {
+  int64_t p = 1;
+  for (int l = 0; l < d.D; ++l) p *= d.nx[l];
+  return p;
+}
+int64_t n_vel(const slmpp_grid_desc& d) {
+  int64_t p = 1;
+  for (int l = 0; l < d.D; ++l) p *= d.nv[l];
+  return p;
+}
+
+Layout layout_of(const slmpp_grid_desc& d) {
+  Layout L{};
+  const int64_t nxs = n_space(d), ncell = nxs * n_vel(d);
+  int64_t sumnx = 0, sumnv = 0;
+  for (int l = 0; l < d.D; ++l) {
+    sumnx += d.nx[l];
+    sumnv += d.nv[l];
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  L.rho = take(sizeof(double) * nxs);
+  L.phi = take(sizeof(double) * nxs);
+  L.accel = take(sizeof(double) * nxs * d.D);
+  L.green = take(sizeof(double) * nxs);
+  L.bufA = take(sizeof(double2) * nxs);
+  L.bufB = take(sizeof(double2) * nxs);
+  L.tw = take(sizeof(double2) * sumnx);
+  L.partials = take(sizeof(double) * kDiagBlocks * 5);
+  L.diagfield = take(sizeof(double) * 4);
+  L.stage_doubles = std::max<int64_t>(std::min<int64_t>(kStageChunk, ncell), nxs + sumnv);
+  L.stage = take(sizeof(double) * L.stage_doubles);
+  L.total = off;
+  return L;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) {
+  if (!d) {
+    msg = "desc is NULL";
+    return SLMPP_ERR_INVALID;
+  }
+  if (d->D < 1 || d->D > 3) {
+    msg = "D must be 1, 2 or 3";
+    return SLMPP_ERR_INVALID;
+  }
+  if (d->order != 5 && d->order != 7) {
+    msg = "order must be 5 or 7";
+    return SLMPP_ERR_INVALID;
+  }
+  if (d->limiter < SLMPP_LIM_NONE || d->limiter > SLMPP_LIM_MPP) {
+    msg = "limiter must be SLMPP_LIM_NONE, SLMPP_LIM_MP or SLMPP_LIM_MPP";
+    return SLMPP_ERR_INVALID;
+  }
+  if (d->poisson_order != 2 && d->poisson_order != 4 && d->poisson_order != 6) {
+    msg = "poisson_order must be 2, 4 or 6";
+    return SLMPP_ERR_INVALID;
+  }
+  if (d->storage != SLMPP_F64 && d->storage != SLMPP_F32) {
+    msg = "storage must be SLMPP_F64 or SLMPP_F32";
+    return SLMPP_ERR_INVALID;
+  }
+  if ((d->x_bc != SLMPP_BC_PERIODIC && d->x_bc != SLMPP_BC_OUTFLOW) ||
+      (d->v_bc != SLMPP_BC_PERIODIC && d->v_bc != SLMPP_BC_OUTFLOW)) {
+    msg = "x_bc / v_bc must be SLMPP_BC_PERIODIC or SLMPP_BC_OUTFLOW";
+    return SLMPP_ERR_INVALID;
+  }
+  if (d->flags != 0) {
+    msg = "flags must be 0";
+    return SLMPP_ERR_INVALID;
+  }
+  if (!finite(d->alpha) || !(d->alpha > 0.0) || !finite(d->kappa)) {
+    msg = "alpha must be finite and > 0, kappa finite";
+    return SLMPP_ERR_NONFINITE;
+  }
+  int64_t cells = 1;
+  for (int l = 0; l < d->D; ++l) {
+    if (d->nx[l] < 1 || d->nx[l] > kMaxAxis || d->nv[l] < 1 || d->nv[l] > kMaxAxis) {
+      msg = "every axis needs 1..4096 cells";
+      return SLMPP_ERR_SHAPE;
+    }
+    if (!finite(d->x_lo[l]) || !finite(d->x_hi[l]) || !finite(d->v_lo[l]) ||
+        !finite(d->v_hi[l])) {
+      msg = "domain bounds must be finite";
+      return SLMPP_ERR_NONFINITE;
+    }
+    if (!(d->x_hi[l] > d->x_lo[l]) || !(d->v_hi[l] > d->v_lo[l])) {
+      msg = "domain bounds need hi > lo";
+      return SLMPP_ERR_SHAPE;
+    }
+    cells *= d->nx[l];
+    cells *= d->nv[l];
+    if (cells > kMaxCells) {
+      msg = "grid exceeds 2^40 cells";
+      return SLMPP_ERR_SHAPE;
+    }
+  }
+  return SLMPP_OK;
+}
+
+}  // namespace
+
+struct slmpp_ctx {
+  slmpp_grid_desc d{};
+  void* f = nullptr;
+  char* work = nullptr;
+  size_t work_bytes = 0;
+  hipStream_t stream = nullptr;
+  Layout lay{};
+  int D = 1;
+  int64_t dims[6]{};
+  int64_t nxs = 0, nvs = 0, ncell = 0;
+  double hx[3]{}, hv[3]{};
+  int64_t tw_off[3]{};
+  bool field_valid = false;
+  std::string err;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_class;
+  std::vector<double> ev_bytes, ev_cells;
+  slmpp_timing acc{};
+
+  double* rho() { return reinterpret_cast<double*>(work + lay.rho); }
+  double* phi() { return reinterpret_cast<double*>(work + lay.phi); }
+  double* accel() { return reinterpret_cast<double*>(work + lay.accel); }
+  double* green() { return reinterpret_cast<double*>(work + lay.green); }
+  double2* bufA() { return reinterpret_cast<double2*>(work + lay.bufA); }
+  double2* bufB() { return reinterpret_cast<double2*>(work + lay.bufB); }
+  double2* tw() { return reinterpret_cast<double2*>(work + lay.tw); }
+  double* partials() { return reinterpret_cast<double*>(work + lay.partials); }
+  double* diagfield() { return reinterpret_cast<double*>(work + lay.diagfield); }
+  double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
+  size_t esize() const { return d.storage == SLMPP_F64 ? 8 : 4; }
+
+  slmpp_status fail(slmpp_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  slmpp_status hip_fail(hipError_t e, const char* what) {
+    return fail(SLMPP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+
+  // --- timing brackets ---
+  hipError_t tic(int cls, double bytes, double cells) {
+    if (!timing) return hipSuccess;
+    while (ev_pool.size() < ev_used + 2) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev_pool.push_back(e);
+    }
+    ev_class.push_back(cls);
+    ev_bytes.push_back(bytes);
+    ev_cells.push_back(cells);
+    return hipEventRecord(ev_pool[ev_used++], stream);
+  }
+  hipError_t toc() {
+    if (!timing) return hipSuccess;
+    return hipEventRecord(ev_pool[ev_used++], stream);
+  }
+  hipError_t collect() {
+    if (ev_used == 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    for (size_t k = 0; k < ev_class.size(); ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev_pool[2 * k], ev_pool[2 * k + 1]);
+      if (e != hipSuccess) return e;
+      const int c = ev_class[k];
+      acc.launches[c] += 1;
+      acc.total_ms[c] += ms;
+      acc.bytes[c] += ev_bytes[k];
+      acc.cells[c] += ev_cells[k];
+    }
+    ev_used = 0;
+    ev_class.clear();
+    ev_bytes.clear();
+    ev_cells.clear();
+    return hipSuccess;
+  }
+
+  // --- one sweep along array axis a ---
+  slmpp_status sweep(int a, double dt, const double* accel_dev) {
+    const int nd = 2 * D;
+    int64_t inner = 1;
+    for (int k = a + 1; k < nd; ++k) inner *= dims[k];
+    int64_t outer = 1;
+    for (int k = 0; k < a; ++k) outer *= dims[k];
+    SweepArgs s{};
+    s.f = f;
+    s.npen = outer * inner;
+    s.inner = inner;
+    s.n = (int32_t)dims[a];
+    s.dt = dt;
+    s.alpha = d.alpha;
+    if (a < D) {  // x_l sweep, speed v_l
+      const int l = a;
+      int64_t vdiv = 1;
+      for (int k = D + l + 1; k < nd; ++k) vdiv *= dims[k];
+      s.cmode = SPEED_FROM_VELOCITY;
+      s.vdiv = vdiv;
+      s.nvl = (int32_t)d.nv[l];
+      s.vlo = d.v_lo[l];
+      s.dv = hv[l];
+      s.h = hx[l];
+      s.bc = d.x_bc;
+      s.xdiv = 1;
+      s.nfast = max_shift_velocity(s.vlo, s.dv, s.nvl, dt, s.h, s.n, s.bc);
+    } else {  // v_l sweep, speed a_l(x)
+      const int l = a - D;
+      int64_t xdiv = 1;
+      for (int k = D; k < a; ++k) xdiv *= dims[k];
+      s.cmode = SPEED_FROM_ACCEL;
+      s.accel = accel_dev;
+      s.xdiv = xdiv;
+      s.vdiv = 1;
+      s.nvl = 1;
+      s.h = hv[l];
+      s.bc = d.v_bc;
+      s.nfast = 2;
+    }
+    SweepPlan p = plan_sweep(d.storage, d.order, s.n, s.npen, inner, s.nfast);
+    if (p.lds_bytes > 160 * 1024)
+      return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
+    const double cells = (double)ncell;
+    hipError_t e = tic(inner == 1 ? 1 : 0, 2.0 * cells * esize(), cells);
+    if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, stream);
+    if (e == hipSuccess) e = toc();
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    return SLMPP_OK;
+  }
+
+  slmpp_status moment(double* rho_dev) {
+    double dvol = 1.0;
+    for (int l = 0; l < D; ++l) dvol *= hv[l];
+    hipError_t e = tic(2, (double)ncell * esize() + 8.0 * nxs, 0.0);
+    if (e == hipSuccess) e = launch_moment(d.storage, f, nxs, nvs, dvol, rho_dev, stream);
+    if (e == hipSuccess) e = toc();
+    if (e != hipSuccess) return hip_fail(e, "moment launch");
+    return SLMPP_OK;
+  }
+
+  slmpp_status poisson(const double* rho_dev, double* phi_dev, double* accel_dev) {
+    hipError_t e = tic(3, 8.0 * nxs * (2 + D), 0.0);
+    if (e == hipSuccess)
+      e = launch_poisson(rho_dev, phi_dev ? phi_dev : phi(), accel_dev, bufA(), bufB(), tw(),
+                         tw_off, green(), D, d.nx, hx, d.poisson_order, stream);
+    if (e == hipSuccess) e = toc();
+    if (e != hipSuccess) return hip_fail(e, "poisson launch");
+    return SLMPP_OK;
+  }
+
+  slmpp_status field() {
+    slmpp_status st = moment(rho());
+    if (st == SLMPP_OK) st = poisson(rho(), phi(), accel());
+    if (st == SLMPP_OK) field_valid = true;
+    return st;
+  }
+};
+
+namespace {
+
+// Laplacian symbol times Delta^2 of the 2nd/4th/6th-order stencils of
+// App. C (sum of one-dimensional symbols for several axes).
+double lap_symbol(double th, int order) {
+  const double a = std::sin(0.5 * th), b = std::sin(th), c = std::sin(1.5 * th);
+  if (order == 2) return -4.0 * a * a;
+  if (order == 4) return (b * b - 16.0 * a * a) / 3.0;
+  return (-2.0 * c * c + 27.0 * b * b - 270.0 * a * a) / 45.0;
+}
+
+slmpp_status sync_status(slmpp_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "stream synchronize");
+  return SLMPP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t slmpp_abi_version(void) { return SLMPP_ABI_VERSION; }
+
+size_t slmpp_workspace_bytes(const slmpp_grid_desc* desc) {
+  std::string msg;
+  if (check_desc(desc, msg) != SLMPP_OK) return 0;
+  return layout_of(*desc).total;
+}
+
+slmpp_status slmpp_validate(const slmpp_grid_desc* desc, char* msg, size_t msg_len) {
+  std::string m;
+  slmpp_status st = check_desc(desc, m);
+  if (msg && msg_len) {
+    std::snprintf(msg, msg_len, "%s", m.c_str());
+  }
+  if (st != SLMPP_OK) g_error = m;
+  return st;
+}
+
+slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_dev,
+                          size_t work_bytes, void* hip_stream, slmpp_ctx** out) {
+  try {
+    std::string msg;
+    if (!out) {
+      g_error = "out is NULL";
+      return SLMPP_ERR_INVALID;
+    }
+    *out = nullptr;
+    slmpp_status st = check_desc(desc, msg);
+    if (st != SLMPP_OK) {
+      g_error = msg;
+      return st;
+    }
+    if (!f_dev || !work_dev) {
+      g_error = "f_dev and work_dev must be non-NULL";
+      return SLMPP_ERR_INVALID;
+    }
+    if (reinterpret_cast<uintptr_t>(work_dev) % 256 != 0 ||
+        reinterpret_cast<uintptr_t>(f_dev) % 16 != 0) {
+      g_error = "work_dev must be 256-byte and f_dev 16-byte aligned";
+      return SLMPP_ERR_INVALID;
+    }
+    Layout lay = layout_of(*desc);
+    if (work_bytes < lay.total) {
+      g_error = "workspace of " + std::to_string(work_bytes) + " bytes, need " +
+                std::to_string(lay.total);
+      return SLMPP_ERR_WORKSPACE;
+    }
+    slmpp_ctx* c = new slmpp_ctx();
+    c->d = *desc;
+    c->f = f_dev;
+    c->work = static_cast<char*>(work_dev);
+    c->work_bytes = work_bytes;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->lay = lay;
+    c->D = desc->D;
+    for (int l = 0; l < c->D; ++l) {
+      c->dims[l] = desc->nx[l];
+      c->dims[c->D + l] = desc->nv[l];
+      c->hx[l] = (desc->x_hi[l] - desc->x_lo[l]) / (double)desc->nx[l];
+      c->hv[l] = (desc->v_hi[l] - desc->v_lo[l]) / (double)desc->nv[l];
+    }
+    c->nxs = n_space(*desc);
+    c->nvs = n_vel(*desc);
+    c->ncell = c->nxs * c->nvs;
+    // Green function table and twiddles
+    std::vector<double> green(c->nxs);
+    for (int64_t idx = 0; idx < c->nxs; ++idx) {
+      int64_t rem = idx;
+      int64_t k[3] = {0, 0, 0};
+      for (int l = c->D - 1; l >= 0; --l) {
+        k[l] = rem % desc->nx[l];
+        rem /= desc->nx[l];
+      }
+      double L = 0.0;
+      bool zero = true;
+      for (int l = 0; l < c->D; ++l) {
+        if (k[l]) zero = false;
+        const double th = 2.0 * M_PI * (double)k[l] / (double)desc->nx[l];
+        L += lap_symbol(th, desc->poisson_order) / (c->hx[l] * c->hx[l]);
+      }
+      green[idx] = zero ? 0.0 : desc->kappa / L;
+    }
+    std::vector<double2> tw;
+    for (int l = 0; l < c->D; ++l) {
+      c->tw_off[l] = (int64_t)tw.size();
+      for (int64_t q = 0; q < desc->nx[l]; ++q) {
+        const double ang = 2.0 * M_PI * (double)q / (double)desc->nx[l];
+        tw.push_back(make_double2(std::cos(ang), -std::sin(ang)));
+      }
+    }
+    hipError_t e = hipMemcpyAsync(c->green(), green.data(), sizeof(double) * green.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->tw(), tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice,
+                         c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      g_error = std::string("upload of field tables: ") + hipGetErrorString(e);
+      delete c;
+      return SLMPP_ERR_DEVICE;
+    }
+    *out = c;
+    return SLMPP_OK;
+  } catch (const std::bad_alloc&) {
+    g_error = "host allocation failed";
+    return SLMPP_ERR_DEVICE;
+  }
+}
+
+slmpp_status slmpp_destroy(slmpp_ctx* ctx) {
+  if (!ctx) return SLMPP_ERR_INVALID;
+  if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return SLMPP_OK;
+}
+
+const char* slmpp_last_error(const slmpp_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_error.c_str();
+}
+
+slmpp_status slmpp_init_f_host(slmpp_ctx* c, const double* f_host, int64_t n) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!f_host) return c->fail(SLMPP_ERR_INVALID, "f_host is NULL");
+  if (n != c->ncell) return c->fail(SLMPP_ERR_SHAPE, "n = %lld, grid has %lld cells", (long long)n, (long long)c->ncell);
+  const int64_t chunk = c->lay.stage_doubles;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = std::min(chunk, n - off);
+    hipError_t e = hipMemcpyAsync(c->stage(), f_host + off, sizeof(double) * m,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = launch_from_double(c->d.storage, static_cast<char*>(c->f) + off * c->esize(), c->stage(), m,
+                             c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "init_f_host");
+  }
+  c->field_valid = false;
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_init_f_separable(slmpp_ctx* c, const double* s_host, const double* g1,
+                                    const double* g2, const double* g3) {
+  if (!c) return SLMPP_ERR_INVALID;
+  const double* g[3] = {g1, g2, g3};
+  if (!s_host) return c->fail(SLMPP_ERR_INVALID, "s_host is NULL");
+  for (int l = 0; l < c->D; ++l)
+    if (!g[l]) return c->fail(SLMPP_ERR_INVALID, "velocity factor %d is NULL", l + 1);
+  double* st = c->stage();
+  hipError_t e = hipMemcpyAsync(st, s_host, sizeof(double) * c->nxs, hipMemcpyHostToDevice, c->stream);
+  const double* gd[3] = {nullptr, nullptr, nullptr};
+  int64_t off = c->nxs;
+  for (int l = 0; l < c->D && e == hipSuccess; ++l) {
+    gd[l] = st + off;
+    e = hipMemcpyAsync(st + off, g[l], sizeof(double) * c->d.nv[l], hipMemcpyHostToDevice, c->stream);
+    off += c->d.nv[l];
+  }
+  if (e == hipSuccess)
+    e = launch_init_separable(c->d.storage, c->f, st, gd[0], gd[1], gd[2], c->D, c->d.nv, c->nxs,
+                              c->nvs, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "init_f_separable");
+  c->field_valid = false;
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_advect_x(slmpp_ctx* c, int32_t dim, double dt) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (dim < 0 || dim >= c->D) return c->fail(SLMPP_ERR_INVALID, "dim %d outside 0..%d", dim, c->D - 1);
+  if (!std::isfinite(dt)) return c->fail(SLMPP_ERR_NONFINITE, "dt is not finite");
+  c->field_valid = false;
+  if (dt == 0.0) return SLMPP_OK;
+  return c->sweep(dim, dt, nullptr);
+}
+
+slmpp_status slmpp_advect_v(slmpp_ctx* c, int32_t dim, double dt, const double* accel_dev) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (dim < 0 || dim >= c->D) return c->fail(SLMPP_ERR_INVALID, "dim %d outside 0..%d", dim, c->D - 1);
+  if (!std::isfinite(dt)) return c->fail(SLMPP_ERR_NONFINITE, "dt is not finite");
+  if (!accel_dev) return c->fail(SLMPP_ERR_INVALID, "accel_dev is NULL");
+  c->field_valid = false;
+  if (dt == 0.0) return SLMPP_OK;
+  return c->sweep(c->D + dim, dt, accel_dev);
+}
+
+slmpp_status slmpp_density_moment(slmpp_ctx* c, double* rho_dev) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!rho_dev) return c->fail(SLMPP_ERR_INVALID, "rho_dev is NULL");
+  return c->moment(rho_dev);
+}
+
+slmpp_status slmpp_poisson_solve(slmpp_ctx* c, const double* rho_dev, double* phi_dev,
+                                 double* accel_dev) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!rho_dev || !accel_dev) return c->fail(SLMPP_ERR_INVALID, "rho_dev and accel_dev must be non-NULL");
+  return c->poisson(rho_dev, phi_dev, accel_dev);
+}
+
+slmpp_status slmpp_field(slmpp_ctx* c) {
+  if (!c) return SLMPP_ERR_INVALID;
+  return c->field();
+}
+
+slmpp_status slmpp_field_ptrs(const slmpp_ctx* cc, const double** rho_dev, const double** phi_dev,
+                              const double** accel_dev) {
+  if (!cc) return SLMPP_ERR_INVALID;
+  slmpp_ctx* c = const_cast<slmpp_ctx*>(cc);
+  if (rho_dev) *rho_dev = c->rho();
+  if (phi_dev) *phi_dev = c->phi();
+  if (accel_dev) *accel_dev = c->accel();
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_get_field(slmpp_ctx* c, double* rho_host, double* accel_host) {
+  if (!c) return SLMPP_ERR_INVALID;
+  hipError_t e = hipSuccess;
+  if (rho_host)
+    e = hipMemcpyAsync(rho_host, c->rho(), sizeof(double) * c->nxs, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && accel_host)
+    e = hipMemcpyAsync(accel_host, c->accel(), sizeof(double) * c->nxs * c->D,
+                       hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "get_field");
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!std::isfinite(dt)) return c->fail(SLMPP_ERR_NONFINITE, "dt is not finite");
+  if (nsteps < 1) return c->fail(SLMPP_ERR_INVALID, "nsteps must be >= 1");
+  const int D = c->D;
+  for (int32_t it = 0; it < nsteps; ++it) {
+    slmpp_status st = SLMPP_OK;
+    if (!c->field_valid) st = c->field();
+    for (int l = 0; l < D && st == SLMPP_OK; ++l)
+      st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
+    for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l) st = c->sweep(l, dt, nullptr);
+    if (st == SLMPP_OK) st = c->field();
+    for (int l = 0; l < D && st == SLMPP_OK; ++l)
+      st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
+    if (st != SLMPP_OK) {
+      c->field_valid = false;
+      return st;
+    }
+  }
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_get_f(slmpp_ctx* c, double* f_host, int64_t n) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!f_host) return c->fail(SLMPP_ERR_INVALID, "f_host is NULL");
+  if (n != c->ncell) return c->fail(SLMPP_ERR_SHAPE, "n = %lld, grid has %lld cells", (long long)n, (long long)c->ncell);
+  const int64_t chunk = c->lay.stage_doubles;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = std::min(chunk, n - off);
+    hipError_t e = launch_to_double(c->d.storage, static_cast<const char*>(c->f) + off * c->esize(),
+                                    c->stage(), m, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(f_host + off, c->stage(), sizeof(double) * m, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "get_f");
+  }
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_diag(slmpp_ctx* c, slmpp_diag_out* out) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!out) return c->fail(SLMPP_ERR_INVALID, "out is NULL");
+  slmpp_status st = SLMPP_OK;
+  if (!c->field_valid) st = c->field();
+  if (st != SLMPP_OK) return st;
+  const int nb = kDiagBlocks;
+  hipError_t e = launch_diag_f(c->d.storage, c->f, c->ncell, c->partials(), nb, c->stream);
+  int64_t inner1 = 1;
+  for (int l = 1; l < c->D; ++l) inner1 *= c->d.nx[l];
+  if (e == hipSuccess)
+    e = launch_diag_field(c->accel(), c->D, c->nxs, c->d.nx[0], inner1, c->diagfield(), c->stream);
+  std::vector<double> part(nb * 5);
+  double fld[3];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), c->partials(), sizeof(double) * nb * 5, hipMemcpyDeviceToHost,
+                       c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(fld, c->diagfield(), sizeof(double) * 3, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "diag");
+  double s = 0.0, comp = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double x = part[b * 4 + 0];
+    const double t = s + x;
+    comp += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+    comp += part[b * 4 + 1];
+    mn = std::min(mn, part[b * 4 + 2]);
+    mx = std::max(mx, part[b * 4 + 3]);
+    bad += part[nb * 4 + b];
+  }
+  double vol = 1.0, dxv = 1.0;
+  for (int l = 0; l < c->D; ++l) {
+    vol *= c->hx[l] * c->hv[l];
+    dxv *= c->hx[l];
+  }
+  out->mass = vol * (s + comp);
+  out->f_min = mn;
+  out->f_max = mx;
+  out->nonfinite = (int64_t)bad;
+  out->field_energy = 0.5 * fld[0] * dxv;
+  out->mode_amp = std::sqrt(fld[1] * fld[1] + fld[2] * fld[2]) / (double)c->nxs;
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_sync(slmpp_ctx* c) {
+  if (!c) return SLMPP_ERR_INVALID;
+  return sync_status(c);
+}
+
+slmpp_status slmpp_timing_enable(slmpp_ctx* c, int32_t on) {
+  if (!c) return SLMPP_ERR_INVALID;
+  hipError_t e = c->collect();
+  if (e != hipSuccess) return c->hip_fail(e, "timing");
+  c->timing = on != 0;
+  c->acc = slmpp_timing{};
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_timing_read(slmpp_ctx* c, slmpp_timing* out) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!out) return c->fail(SLMPP_ERR_INVALID, "out is NULL");
+  hipError_t e = c->collect();
+  if (e != hipSuccess) return c->hip_fail(e, "timing");
+  *out = c->acc;
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_copy_device(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream) {
+  if (!dst_dev || !src_dev) {
+    g_error = "copy: NULL pointer";
+    return SLMPP_ERR_INVALID;
+  }
+  if (reinterpret_cast<uintptr_t>(dst_dev) % 16 || reinterpret_cast<uintptr_t>(src_dev) % 16 ||
+      bytes % 16) {
+    g_error = "copy: pointers and size must be multiples of 16 bytes";
+    return SLMPP_ERR_INVALID;
+  }
+  hipError_t e = launch_copy(dst_dev, src_dev, bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) {
+    g_error = std::string("copy: ") + hipGetErrorString(e);
+    return SLMPP_ERR_DEVICE;
+  }
+  return SLMPP_OK;
+}
+
+}  // extern "C"

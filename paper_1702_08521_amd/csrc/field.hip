@@ -1,0 +1,376 @@
+// Field kernels: velocity moment, periodic Poisson solve with high-order
+// Green functions and forces (Sec. 2.2, App. C), initialisation, and
+// reductions for diagnostics.  All field arithmetic is double precision.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "slmpp_internal.hpp"
+
+namespace slmpp {
+namespace {
+
+// ---- compensated (Neumaier) accumulation ------------------------------
+struct KSum {
+  double s, c;
+};
+__device__ __forceinline__ void kadd(KSum& a, double x) {
+  const double t = a.s + x;
+  if (fabs(a.s) >= fabs(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+__device__ __forceinline__ void kmerge(KSum& a, const KSum& b) {
+  kadd(a, b.s);
+  a.c += b.c;
+}
+
+template <int NT>
+__device__ KSum block_ksum(KSum v) {
+  __shared__ double ss[NT], sc[NT];
+  ss[threadIdx.x] = v.s;
+  sc[threadIdx.x] = v.c;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      KSum a{ss[threadIdx.x], sc[threadIdx.x]};
+      KSum b{ss[threadIdx.x + off], sc[threadIdx.x + off]};
+      kmerge(a, b);
+      ss[threadIdx.x] = a.s;
+      sc[threadIdx.x] = a.c;
+    }
+    __syncthreads();
+  }
+  KSum r{ss[0], sc[0]};
+  __syncthreads();
+  return r;
+}
+
+// rho[ix] = dvol * sum over the contiguous velocity block of cell ix.
+// One workgroup per spatial cell; fixed reduction order (deterministic).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) moment_kernel(const T* __restrict__ f, int64_t nvs,
+                                                    double dvol, double* __restrict__ rho) {
+  const T* b = f + (int64_t)blockIdx.x * nvs;
+  KSum acc{0.0, 0.0};
+  for (int64_t k = threadIdx.x; k < nvs; k += NT) kadd(acc, (double)b[k]);
+  KSum tot = block_ksum<NT>(acc);
+  if (threadIdx.x == 0) rho[blockIdx.x] = dvol * (tot.s + tot.c);
+}
+
+// ---- discrete Fourier transform along one axis ------------------------
+// out[o, k, j] = sum_m in[o, m, j] * tw[(m k) mod n]^sign, tw[q] = exp(-2 pi i q / n)
+__global__ void dft_axis_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                int64_t total, int64_t n, int64_t inner,
+                                const double2* __restrict__ tw, int conj) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t j = t % inner;
+  const int64_t k = (t / inner) % n;
+  const int64_t o = t / (inner * n);
+  const double2* src = in + o * n * inner + j;
+  double sr = 0.0, si = 0.0;
+  int64_t q = 0;
+  for (int64_t m = 0; m < n; ++m) {
+    const double2 x = src[m * inner];
+    const double2 w = tw[q];
+    const double wi = conj ? -w.y : w.y;
+    sr += x.x * w.x - x.y * wi;
+    si += x.x * wi + x.y * w.x;
+    q += k;
+    if (q >= n) q -= n;
+  }
+  out[t] = make_double2(sr, si);
+}
+
+__global__ void real_to_complex_kernel(const double* __restrict__ r, double2* __restrict__ c,
+                                       int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) c[t] = make_double2(r[t], 0.0);
+}
+
+__global__ void green_kernel(double2* __restrict__ c, const double* __restrict__ g, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    const double2 v = c[t];
+    c[t] = make_double2(v.x * g[t], v.y * g[t]);
+  }
+}
+
+__global__ void complex_to_real_kernel(const double2* __restrict__ c, double* __restrict__ r,
+                                       int64_t n, double scale) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) r[t] = c[t].x * scale;
+}
+
+// accel_l = -dphi/dx_l by the periodic 2-, 4- or 6-point FDA (App. C)
+__global__ void fda_kernel(const double* __restrict__ phi, double* __restrict__ accel,
+                           int64_t total, int64_t n, int64_t inner, double h, int order) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t i = (t / inner) % n;
+  const double* base = phi + (t - i * inner);
+  auto P = [&](int64_t k) {
+    int64_t r = (i + k) % n;
+    if (r < 0) r += n;
+    return base[r * inner];
+  };
+  double d;
+  if (order == 2)
+    d = (P(1) - P(-1)) / (2.0 * h);
+  else if (order == 4)
+    d = (8.0 * (P(1) - P(-1)) - (P(2) - P(-2))) / (12.0 * h);
+  else
+    d = (45.0 * (P(1) - P(-1)) - 9.0 * (P(2) - P(-2)) + (P(3) - P(-3))) / (60.0 * h);
+  accel[t] = -d;
+}
+
+// ---- initialisation and conversions -----------------------------------
+template <typename T>
+__global__ void init_separable_kernel(T* __restrict__ f, const double* __restrict__ s,
+                                      const double* __restrict__ g1, const double* __restrict__ g2,
+                                      const double* __restrict__ g3, int D, int64_t nv1,
+                                      int64_t nv2, int64_t nv3, int64_t nvs, int64_t total) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ix = t / nvs;
+    int64_t iv = t - ix * nvs;
+    double v = s[ix];
+    if (D == 1) {
+      v = v * g1[iv];
+    } else if (D == 2) {
+      const int64_t j2 = iv % nv2, j1 = iv / nv2;
+      v = v * g1[j1];
+      v = v * g2[j2];
+    } else {
+      const int64_t j3 = iv % nv3;
+      iv /= nv3;
+      const int64_t j2 = iv % nv2, j1 = iv / nv2;
+      v = v * g1[j1];
+      v = v * g2[j2];
+      v = v * g3[j3];
+    }
+    f[t] = (T)v;
+  }
+  (void)nv1;
+}
+
+template <typename T>
+__global__ void from_double_kernel(T* __restrict__ f, const double* __restrict__ src, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    f[t] = (T)src[t];
+}
+
+template <typename T>
+__global__ void to_double_kernel(const T* __restrict__ f, double* __restrict__ dst, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = (double)f[t];
+}
+
+// ---- diagnostics --------------------------------------------------------
+// partials[b*4 + 0..3] = (sum, compensation, min, max) and
+// partials[nblocks*4 + b] = count of non-finite values, per block b.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) diag_f_kernel(const T* __restrict__ f, int64_t n,
+                                                    double* __restrict__ partials) {
+  KSum acc{0.0, 0.0};
+  double mn = INFINITY, mx = -INFINITY;
+  double bad = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) {
+    const double v = (double)f[t];
+    if (!isfinite(v)) {
+      bad += 1.0;
+      continue;
+    }
+    kadd(acc, v);
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  KSum tot = block_ksum<NT>(acc);
+  __shared__ double smn[NT], smx[NT], sbad[NT];
+  smn[threadIdx.x] = mn;
+  smx[threadIdx.x] = mx;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + off]);
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + off]);
+      sbad[threadIdx.x] += sbad[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 4 + 0] = tot.s;
+    partials[blockIdx.x * 4 + 1] = tot.c;
+    partials[blockIdx.x * 4 + 2] = smn[0];
+    partials[blockIdx.x * 4 + 3] = smx[0];
+    partials[(int64_t)gridDim.x * 4 + blockIdx.x] = sbad[0];
+  }
+}
+
+// out[0] = sum |a|^2 over all components and cells; out[1], out[2] =
+// real/imaginary part of sum_x a_1(x) exp(-2 pi i x1_index / nx1).
+template <int NT>
+__global__ void __launch_bounds__(NT) diag_field_kernel(const double* __restrict__ accel, int D,
+                                                        int64_t nxs, int64_t nx1, int64_t inner1,
+                                                        double* __restrict__ out) {
+  KSum e{0.0, 0.0}, cr{0.0, 0.0}, ci{0.0, 0.0};
+  for (int64_t t = threadIdx.x; t < (int64_t)D * nxs; t += NT) {
+    const double a = accel[t];
+    kadd(e, a * a);
+  }
+  for (int64_t t = threadIdx.x; t < nxs; t += NT) {
+    const int64_t i1 = t / inner1;
+    const double ang = -2.0 * M_PI * (double)(i1 % nx1) / (double)nx1;
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    kadd(cr, accel[t] * cs);
+    kadd(ci, accel[t] * sn);
+  }
+  KSum te = block_ksum<NT>(e);
+  KSum tr = block_ksum<NT>(cr);
+  KSum ti = block_ksum<NT>(ci);
+  if (threadIdx.x == 0) {
+    out[0] = te.s + te.c;
+    out[1] = tr.s + tr.c;
+    out[2] = ti.s + ti.c;
+  }
+}
+
+__global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+inline unsigned grid_capped(int64_t n, int nt) {
+  int64_t b = (n + nt - 1) / nt;
+  return (unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+hipError_t launch_moment(int dtype, const void* f, int64_t nxs, int64_t nvs, double dvol,
+                         double* rho, hipStream_t s) {
+  if (nxs <= 0) return hipSuccess;
+  constexpr int NT = 256;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL((moment_kernel<double, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
+                       (const double*)f, nvs, dvol, rho);
+  else
+    hipLaunchKernelGGL((moment_kernel<float, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
+                       (const float*)f, nvs, dvol, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson(const double* rho, double* phi, double* accel, double2* bufA,
+                          double2* bufB, const double2* twiddles, const int64_t* tw_off,
+                          const double* green, int D, const int64_t* nx, const double* h,
+                          int order, hipStream_t s) {
+  int64_t nxs = 1;
+  for (int l = 0; l < D; ++l) nxs *= nx[l];
+  constexpr int NT = 256;
+  hipLaunchKernelGGL(real_to_complex_kernel, dim3(blocks_for(nxs, NT)), dim3(NT), 0, s, rho, bufA,
+                     nxs);
+  double2* cur = bufA;
+  double2* oth = bufB;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int l = 0; l < D; ++l) {
+      int64_t inner = 1;
+      for (int k = l + 1; k < D; ++k) inner *= nx[k];
+      hipLaunchKernelGGL(dft_axis_kernel, dim3(blocks_for(nxs, NT)), dim3(NT), 0, s, cur, oth,
+                         nxs, nx[l], inner, twiddles + tw_off[l], pass);
+      double2* t = cur;
+      cur = oth;
+      oth = t;
+    }
+    if (pass == 0)
+      hipLaunchKernelGGL(green_kernel, dim3(blocks_for(nxs, NT)), dim3(NT), 0, s, cur, green, nxs);
+  }
+  hipLaunchKernelGGL(complex_to_real_kernel, dim3(blocks_for(nxs, NT)), dim3(NT), 0, s, cur, phi,
+                     nxs, 1.0 / (double)nxs);
+  for (int l = 0; l < D; ++l) {
+    int64_t inner = 1;
+    for (int k = l + 1; k < D; ++k) inner *= nx[k];
+    hipLaunchKernelGGL(fda_kernel, dim3(blocks_for(nxs, NT)), dim3(NT), 0, s, phi,
+                       accel + (int64_t)l * nxs, nxs, nx[l], inner, h[l], order);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_separable(int dtype, void* f, const double* sx, const double* g1,
+                                 const double* g2, const double* g3, int D, const int64_t* nv,
+                                 int64_t nxs, int64_t nvs, hipStream_t st) {
+  const int64_t total = nxs * nvs;
+  constexpr int NT = 256;
+  const unsigned grid = grid_capped(total, NT);
+  const int64_t n1 = nv[0], n2 = D > 1 ? nv[1] : 1, n3 = D > 2 ? nv[2] : 1;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL(init_separable_kernel<double>, dim3(grid), dim3(NT), 0, st, (double*)f, sx,
+                       g1, g2, g3, D, n1, n2, n3, nvs, total);
+  else
+    hipLaunchKernelGGL(init_separable_kernel<float>, dim3(grid), dim3(NT), 0, st, (float*)f, sx,
+                       g1, g2, g3, D, n1, n2, n3, nvs, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_double(int dtype, void* f, const double* src, int64_t n, hipStream_t s) {
+  constexpr int NT = 256;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL(from_double_kernel<double>, dim3(grid_capped(n, NT)), dim3(NT), 0, s,
+                       (double*)f, src, n);
+  else
+    hipLaunchKernelGGL(from_double_kernel<float>, dim3(grid_capped(n, NT)), dim3(NT), 0, s,
+                       (float*)f, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_double(int dtype, const void* f, double* dst, int64_t n, hipStream_t s) {
+  constexpr int NT = 256;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL(to_double_kernel<double>, dim3(grid_capped(n, NT)), dim3(NT), 0, s,
+                       (const double*)f, dst, n);
+  else
+    hipLaunchKernelGGL(to_double_kernel<float>, dim3(grid_capped(n, NT)), dim3(NT), 0, s,
+                       (const float*)f, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_f(int dtype, const void* f, int64_t n, double* partials, int nblocks,
+                         hipStream_t s) {
+  constexpr int NT = 256;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL((diag_f_kernel<double, NT>), dim3(nblocks), dim3(NT), 0, s,
+                       (const double*)f, n, partials);
+  else
+    hipLaunchKernelGGL((diag_f_kernel<float, NT>), dim3(nblocks), dim3(NT), 0, s,
+                       (const float*)f, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_field(const double* accel, int D, int64_t nxs, int64_t nx1, int64_t inner1,
+                             double* out, hipStream_t s) {
+  constexpr int NT = 256;
+  hipLaunchKernelGGL((diag_field_kernel<NT>), dim3(1), dim3(NT), 0, s, accel, D, nxs, nx1, inner1,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  constexpr int NT = 256;
+  const int64_t blocks = std::min<int64_t>((n + NT - 1) / NT, 256 * 64);
+  if (n > 0)
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(NT), 0, s,
+                       (const uint4*)src, (uint4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace slmpp

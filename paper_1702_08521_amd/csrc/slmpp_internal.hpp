@@ -1,0 +1,77 @@
+// Internal declarations shared by the HIP translation units of libslmpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "slmpp.h"
+
+namespace slmpp {
+
+// Speed of a pencil: from the velocity cell centre of the pencil (sweeps
+// along x_l) or from an acceleration array indexed by the spatial cell
+// (sweeps along v_l).
+enum SpeedMode : int32_t { SPEED_FROM_VELOCITY = 0, SPEED_FROM_ACCEL = 1 };
+
+// One sweep over an array viewed as [outer][n][inner]: pencil p = o*inner + j
+// holds the elements o*n*inner + i*inner + j, i = 0..n-1.
+struct SweepArgs {
+  void* f;              // float* or double*
+  const double* accel;  // SPEED_FROM_ACCEL: speed of the pencil = accel[(p/inner)/xdiv]
+  int64_t npen;         // outer * inner
+  int64_t inner;        // stride of the swept axis in elements
+  int64_t vdiv;         // SPEED_FROM_VELOCITY: jv = ((p % inner) / vdiv) % nvl
+  int64_t xdiv;
+  double dt, h;         // time step and mesh spacing of the swept axis
+  double vlo, dv;       // velocity axis of SPEED_FROM_VELOCITY
+  double alpha;         // MP parameter
+  int32_t n;            // pencil length
+  int32_t nvl;
+  int32_t bc;           // SLMPP_BC_*
+  int32_t cmode;        // SpeedMode
+  int32_t nfast;        // integer shifts |N| <= nfast read the LDS tile directly
+};
+
+// Tiling of one sweep launch: W pencils per tile, S segments per pencil,
+// W*S threads per workgroup, G ghost rows above and below the tile in LDS.
+struct SweepPlan {
+  int32_t W, S, threads, G, pitch;
+  size_t lds_bytes;
+  int64_t tiles;
+};
+
+// Plans a sweep launch for the given sizes (dtype: SLMPP_F64/F32).
+SweepPlan plan_sweep(int dtype, int order, int32_t n, int64_t npen, int64_t inner, int32_t nfast,
+                     int W_override = 0, int S_override = 0);
+
+hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a,
+                        const SweepPlan& p, hipStream_t s);
+
+// Integer-shift bound of a sweep along x_l: max |N| over the velocity
+// centres of axis l, with the same split as the kernels.
+int32_t max_shift_velocity(double vlo, double dv, int32_t nvl, double dt, double h, int32_t n,
+                           int32_t bc);
+
+// ---- field kernels (field.hip) ----
+hipError_t launch_moment(int dtype, const void* f, int64_t nxs, int64_t nvs, double dvol,
+                         double* rho, hipStream_t s);
+hipError_t launch_poisson(const double* rho, double* phi, double* accel, double2* bufA,
+                          double2* bufB, const double2* twiddles, const int64_t* tw_off,
+                          const double* green, int D, const int64_t* nx, const double* h,
+                          int order, hipStream_t s);
+hipError_t launch_init_separable(int dtype, void* f, const double* s, const double* g1,
+                                 const double* g2, const double* g3, int D, const int64_t* nv,
+                                 int64_t nxs, int64_t nvs, hipStream_t st);
+hipError_t launch_from_double(int dtype, void* f, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_to_double(int dtype, const void* f, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_diag_f(int dtype, const void* f, int64_t n, double* partials, int nblocks,
+                         hipStream_t s);
+hipError_t launch_diag_field(const double* accel, int D, int64_t nxs, int64_t nx1, int64_t inner1,
+                             double* out, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+constexpr int kDiagBlocks = 1024;
+
+}  // namespace slmpp

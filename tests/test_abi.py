@@ -1,0 +1,101 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+header declares, and validates arguments before touching the device."""
+import ctypes
+import re
+
+import pytest
+
+from paper_1702_08521_amd import slmpp, workloads
+
+
+def _declared_symbols():
+    text = open(slmpp.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slmpp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = slmpp.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    # and the binding wraps exactly the declared entry points
+    assert sorted(slmpp.SIGNATURES) == declared
+
+
+def test_abi_version():
+    assert slmpp.lib().slmpp_abi_version() == 1
+
+
+def _desc(**kw):
+    s = workloads.landau_1d1v(nx=16, nv=32)
+    d = slmpp.make_desc(s)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_workspace_bytes_positive_for_valid_desc():
+    assert slmpp.workspace_bytes(_desc()) > 0
+    s3 = workloads.landau_3d3v(n=8)
+    assert slmpp.workspace_bytes(slmpp.make_desc(s3, slmpp.F32)) > 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("D", 0, slmpp.ERR_INVALID),
+    ("D", 4, slmpp.ERR_INVALID),
+    ("order", 6, slmpp.ERR_INVALID),
+    ("limiter", 3, slmpp.ERR_INVALID),
+    ("poisson_order", 3, slmpp.ERR_INVALID),
+    ("storage", 2, slmpp.ERR_INVALID),
+    ("x_bc", 5, slmpp.ERR_INVALID),
+    ("flags", 1, slmpp.ERR_INVALID),
+    ("alpha", float("nan"), slmpp.ERR_NONFINITE),
+    ("alpha", -1.0, slmpp.ERR_NONFINITE),
+])
+def test_validate_rejects_bad_fields(field, value, code):
+    d = _desc(**{field: value})
+    st, msg = slmpp.validate(d)
+    assert st == code and msg
+    assert slmpp.workspace_bytes(d) == 0
+
+
+def test_validate_rejects_bad_axes():
+    d = _desc()
+    d.nx[0] = 0
+    assert slmpp.validate(d)[0] == slmpp.ERR_SHAPE
+    d = _desc()
+    d.nv[0] = 5000
+    assert slmpp.validate(d)[0] == slmpp.ERR_SHAPE
+    d = _desc()
+    d.x_hi[0] = d.x_lo[0]
+    assert slmpp.validate(d)[0] == slmpp.ERR_SHAPE
+    d = _desc()
+    d.v_lo[0] = float("inf")
+    assert slmpp.validate(d)[0] == slmpp.ERR_NONFINITE
+
+
+def test_create_rejects_null_buffers_without_device():
+    L = slmpp.lib()
+    d = _desc()
+    h = ctypes.c_void_p()
+    st = L.slmpp_create(ctypes.byref(d), None, None, 0, None, ctypes.byref(h))
+    assert st == slmpp.ERR_INVALID and not h.value
+    assert b"NULL" in L.slmpp_last_error(None)
+    st = L.slmpp_create(ctypes.byref(d), ctypes.c_void_p(256), ctypes.c_void_p(512), 16, None,
+                        ctypes.byref(h))
+    assert st == slmpp.ERR_WORKSPACE and not h.value
+
+
+def test_null_context_is_rejected():
+    L = slmpp.lib()
+    assert L.slmpp_advect_x(None, 0, 0.1) == slmpp.ERR_INVALID
+    assert L.slmpp_step(None, 0.1, 1) == slmpp.ERR_INVALID
+    assert L.slmpp_destroy(None) == slmpp.ERR_INVALID
+
+
+def test_copy_rejects_misaligned():
+    L = slmpp.lib()
+    assert L.slmpp_copy_device(ctypes.c_void_p(16), ctypes.c_void_p(32), 17, None) == slmpp.ERR_INVALID
+    assert L.slmpp_copy_device(None, ctypes.c_void_p(32), 16, None) == slmpp.ERR_INVALID
