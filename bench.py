@@ -1,0 +1,258 @@
+"""Benchmark: phase-space cell-updates/s per sweep of the SL-MPP Strang step.
+
+Default workload: three-dimensional electrostatic Landau damping at
+48^3 x 48^3 (1.22e10 cells, 48.9 GB of FP32 f), SL-MPP7, CFL 0.2, in-place
+pencil sweeps; one step = 9 sweeps (v1 v2 v3 half, x3 x2 x1, v1 v2 v3 half)
+plus the FP64 velocity moment and Poisson solve.  Inputs are synthetic
+(the analytic initial condition on the grid), resident in HBM before the
+timed region.
+
+Output: one JSON line on stdout.  `value` = sweeps * cells * steps / time
+(whole-job throughput).  `roofline` is for the sweep kernel (the dominant
+kernel), timed per launch with HIP events on the library's stream;
+`cpu_baseline` is the FP64 CPU oracle on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "phase-space cell-updates/s per sweep, FP32 vs FP64, % HBM peak at stated L1"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name, dtype):
+    from paper_1702_08521_amd import workloads as W
+
+    if name == "landau_3d3v":
+        return W.landau_3d3v(n=48, order=7)
+    if name == "jeans_3d3v":
+        return W.jeans_3d3v(n=32, order=5)
+    if name == "landau_nl_1d1v":
+        return W.landau_nl_1d1v()
+    if name == "landau_1d1v":
+        return W.landau_1d1v()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def read_traffic(kernel_key):
+    """HBM traffic per launch from the committed counter summary, or None
+    when the summary is absent or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    ent = t.get(kernel_key)
+    if not ent:
+        return None
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1702_08521_amd", "csrc", "sweep.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if ent.get("sweep_src_sha") != h:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(spec_fn, n_sample):
+    """FP64 oracle: one Strang step of the same workload at n_sample^6."""
+    import oracle as O
+
+    s = spec_fn(n_sample)
+    run = O.Run(s)
+    t0 = time.perf_counter()
+    run.step(s["dt"], 1)
+    dt = time.perf_counter() - t0
+    cells = 1
+    for l in range(s["D"]):
+        cells *= s["nx"][l] * s["nv"][l]
+    sweeps = 3 * s["D"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": sweeps * cells / dt,
+        "unit": "cell-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"one Strang step ({sweeps} sweeps + moment + Poisson), FP64, "
+                  f"{s['name']} at {n_sample}^{s['D']} x {n_sample}^{s['D']}, {dt:.2f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="landau_3d3v")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--fp64-compare", type=int, default=3,
+                    help="steps of the same workload in FP64 storage for the FP32-vs-FP64 line (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        raise SystemExit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1702_08521_amd import slmpp, workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    spec = workload(args.workload, args.dtype)
+    storage = slmpp.F32 if args.dtype == "f32" else slmpp.F64
+    D = spec["D"]
+    cells = int(np.prod(spec["nx"][:D])) * int(np.prod(spec["nv"][:D]))
+    sweeps = 3 * D
+    dt = spec["dt"]
+    log(f"[bench] {spec['name']} cells={cells:.3e} dtype={args.dtype} steps={args.steps} warmup={args.warmup}")
+
+    stream = torch.cuda.Stream(device=dev)
+    ctx = slmpp.Context(slmpp.make_desc(spec, storage), stream=stream, device=dev)
+    s, gv = W.separable_factors(spec)
+    ctx.init_f_separable(s, gv)
+    ctx.field()
+    ctx.sync()
+    log("[bench] initialised")
+    if args.warmup > 0:
+        ctx.step(dt, args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(dt, args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tim = ctx.timing_read()
+    ctx.timing_enable(False)
+    diag = ctx.diag()
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; diag {diag}")
+
+    value = sweeps * cells * args.steps / elapsed
+    # the dominant kernel: the fused sweep (strided and contiguous launches)
+    sw_ms = tim["sweep_strided"]["total_ms"] + tim["sweep_contiguous"]["total_ms"]
+    sw_n = tim["sweep_strided"]["launches"] + tim["sweep_contiguous"]["launches"]
+    es = 4 if storage == slmpp.F32 else 8
+    bytes_per_launch = 2.0 * es * cells
+    avg_ms = sw_ms / max(sw_n, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernel_key = f"sweep_tile_kernel<{'float' if es == 4 else 'double'},{spec['order']},2>/{spec['name']}"
+    traffic = read_traffic(kernel_key)
+    per_class = {}
+    for k, v in tim.items():
+        if v["launches"]:
+            avg = v["total_ms"] / v["launches"]
+            per_class[k] = {"launches": v["launches"], "avg_ms": round(avg, 4),
+                            "GB_s": round(v["bytes"] / v["launches"] / (avg * 1e-3) / 1e9, 1)}
+            if v["cells"]:
+                per_class[k]["cell_updates_per_s"] = v["cells"] / v["launches"] / (avg * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{spec['name']} {spec['nx'][0]}^{D} x {spec['nv'][0]}^{D}, "
+                        f"SL-MPP{spec['order']}, {args.dtype} f, fp64 moment+Poisson",
+            "cells": cells,
+            "sweeps_per_step": sweeps,
+            "dt": dt,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": kernel_key,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": round(avg_ms, 4),
+        },
+        "detail": {"per_class": per_class, "mass": diag["mass"], "f_min": diag["f_min"],
+                   "nonfinite": diag["nonfinite"]},
+    }
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+
+    if args.fp64_compare > 0 and storage == slmpp.F32:
+        # the same workload with FP64 storage on the same GPU
+        ctx64 = slmpp.Context(slmpp.make_desc(spec, slmpp.F64), stream=stream, device=dev)
+        ctx64.init_f_separable(s, gv)
+        ctx64.field()
+        ctx64.step(dt, 1)
+        ctx64.sync()
+        t0 = time.perf_counter()
+        ctx64.step(dt, args.fp64_compare)
+        ctx64.sync()
+        e64 = time.perf_counter() - t0
+        out["detail"]["fp64_same_workload"] = {
+            "steps": args.fp64_compare,
+            "cell_updates_per_s": sweeps * cells * args.fp64_compare / e64,
+            "ms_per_step": e64 / args.fp64_compare * 1e3,
+        }
+        ctx64.close()
+        del ctx64
+        torch.cuda.empty_cache()
+
+    # reference: a plain streaming copy of 4 GiB with the library's copy kernel
+    nbytes = 4 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        slmpp.copy_device(dst.data_ptr(), src.data_ptr(), nbytes, stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(5):
+            slmpp.copy_device(dst.data_ptr(), src.data_ptr(), nbytes, stream)
+        ev1.record(stream)
+    ev1.synchronize()
+    out["detail"]["copy_kernel_GBs"] = round(5 * 2 * nbytes / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline at {args.cpu_sample}^{D}")
+
+        def spec_fn(n):
+            if args.workload == "landau_3d3v":
+                return W.landau_3d3v(n=n, order=7)
+            if args.workload == "jeans_3d3v":
+                return W.jeans_3d3v(n=n, order=5)
+            return workload(args.workload, args.dtype)
+
+        out["cpu_baseline"] = cpu_baseline(spec_fn, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

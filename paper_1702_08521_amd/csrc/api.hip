@@ -26,7 +26,7 @@ thread_local std::string g_error;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, stage, total;
+  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, total;
   int64_t stage_doubles;
 };
 
@@ -64,6 +64,9 @@ Layout layout_of(const slmpp_grid_desc& d) {
   L.tw = take(sizeof(double2) * sumnx);
   L.partials = take(sizeof(double) * kDiagBlocks * 5);
   L.diagfield = take(sizeof(double) * 4);
+  int64_t maxnv = 1;
+  for (int l = 0; l < d.D; ++l) maxnv = std::max<int64_t>(maxnv, d.nv[l]);
+  L.table = take(pencil_table_bytes(SLMPP_F64, std::max<int64_t>(maxnv, nxs)));
   L.stage_doubles = std::max<int64_t>(std::min<int64_t>(kStageChunk, ncell), nxs + sumnv);
   L.stage = take(sizeof(double) * L.stage_doubles);
   L.total = off;
@@ -169,6 +172,7 @@ struct slmpp_ctx {
   double* partials() { return reinterpret_cast<double*>(work + lay.partials); }
   double* diagfield() { return reinterpret_cast<double*>(work + lay.diagfield); }
   double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
+  void* table() { return work + lay.table; }
   size_t esize() const { return d.storage == SLMPP_F64 ? 8 : 4; }
 
   slmpp_status fail(slmpp_status code, const char* fmt, ...) {
@@ -261,14 +265,15 @@ struct slmpp_ctx {
       s.nvl = 1;
       s.h = hv[l];
       s.bc = d.v_bc;
-      s.nfast = 2;
+      s.nfast = 4;
     }
-    SweepPlan p = plan_sweep(d.storage, d.order, s.n, s.npen, inner, s.nfast);
+    SweepPlan p = plan_sweep(d.storage, d.order, d.limiter, s.n, s.npen, inner, s.nfast);
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
     const double cells = (double)ncell;
     hipError_t e = tic(inner == 1 ? 1 : 0, 2.0 * cells * esize(), cells);
-    if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, stream);
+    const int64_t tcount = a < D ? d.nv[a] : nxs;
+    if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), tcount, stream);
     if (e == hipSuccess) e = toc();
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     return SLMPP_OK;

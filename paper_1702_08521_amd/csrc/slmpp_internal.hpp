@@ -37,17 +37,21 @@ struct SweepArgs {
 // Tiling of one sweep launch: W pencils per tile, S segments per pencil,
 // W*S threads per workgroup, G ghost rows above and below the tile in LDS.
 struct SweepPlan {
-  int32_t W, S, threads, G, pitch;
+  int32_t W, S, R, threads, G, pitch;  // R: cells per thread (0: runtime length)
+  int32_t fast;                        // use the persistent prefetching kernel
   size_t lds_bytes;
   int64_t tiles;
 };
 
 // Plans a sweep launch for the given sizes (dtype: SLMPP_F64/F32).
-SweepPlan plan_sweep(int dtype, int order, int32_t n, int64_t npen, int64_t inner, int32_t nfast,
-                     int W_override = 0, int S_override = 0);
+SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen, int64_t inner,
+                     int32_t nfast, int W_override = 0, int S_override = 0);
 
+// Enqueue the pencil table (table_count entries, one per distinct speed)
+// and the sweep.  `table` is device scratch of pencil_table_bytes().
 hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a,
-                        const SweepPlan& p, hipStream_t s);
+                        const SweepPlan& p, void* table, int64_t table_count, hipStream_t s);
+size_t pencil_table_bytes(int dtype, int64_t count);
 
 // Integer-shift bound of a sweep along x_l: max |N| over the velocity
 // centres of axis l, with the same split as the kernels.

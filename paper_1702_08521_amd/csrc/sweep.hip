@@ -7,20 +7,22 @@
 //   Phibar         =  MP constraint (App. A) on the 5-point stencil
 //   Phihat         =  PP flux limiter (Sec. 2.1.1)
 //   f_i^{n+1}      =  f_{i-N} - zeta (Phihat_{i+1/2} - Phihat_{i-1/2})
-// For zeta < 0 the shifted pencil is processed in reverse order, which is
-// the mirror image of the c > 0 construction the paper writes out.
+// For zeta < 0 the shifted pencil is processed in reverse order, the
+// mirror image of the c > 0 construction the paper writes out.
 //
-// Data movement: a workgroup owns a tile of W whole pencils.  It streams
-// the tile from HBM into LDS once (coalesced along the contiguous axis,
-// whichever way the pencils run), fills ghost rows (periodic images or
-// zeros), computes every pencil from LDS with a register sliding window
-// (each interface flux is computed once and reused by both neighbouring
-// cells), stages the results in LDS and streams them back in place.  So a
-// sweep costs one HBM read and one HBM write of f; stencil halos never
-// leave the chip.  The same kernel serves strided axes (a tile row is W
-// consecutive elements) and the contiguous axis (a tile is W consecutive
-// pencils, transposed through LDS); the LDS row pitch W+1 keeps both the
-// staging writes and the per-pencil reads free of bank conflicts.
+// Two kernels per sweep:
+//  * pencil_table_kernel: one entry per distinct speed (a velocity cell
+//    centre for x-sweeps, a spatial cell for v-sweeps) holding the integer
+//    shift, direction, |zeta| and the CSL flux as FIR weights w_k(|zeta|),
+//    all computed in FP64 (rounded once to the storage type).
+//  * sweep_kernel: a workgroup owns a tile of W whole pencils.  It streams
+//    the tile from HBM into LDS once (16-byte vectors, coalesced along the
+//    contiguous axis whichever way the pencils run), adds ghost rows
+//    (periodic images or zeros), advances every pencil from LDS with a
+//    register sliding window (each interface flux computed once and used
+//    by both neighbouring cells; each thread owns a segment of R cells),
+//    writes the results back into the LDS tile and streams it out in place.
+//    A sweep therefore reads and writes f exactly once; halos stay on chip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,16 +34,14 @@
 namespace slmpp {
 namespace {
 
-enum : int32_t { READ_DIRECT = 0, READ_WRAP = 1, READ_CLAMP = 2 };
-
 template <typename T>
-struct alignas(8) ColParam {
-  T w[7];        // FIR weights of the CSL flux at |zeta|
+struct alignas(16) PencilEntry {
+  T w[7];        // FIR weights of the CSL flux at |zeta| (first ORDER used)
   T z;           // |zeta|
-  int32_t base;  // physical row read at processing position 0 (before wrap)
+  int32_t base;  // physical row read at processing position 0
   int32_t dir;   // +1 forward, -1 mirrored (zeta < 0)
-  int32_t mode;  // READ_*
-  int32_t valid;
+  int32_t absN;  // |N| after periodic reduction
+  int32_t pad;
 };
 
 // CSL flux as an FIR filter: Phi_{i-1/2} = sum_k w_k(zeta) f_{i-h+k} with
@@ -81,15 +81,10 @@ __device__ __forceinline__ double departure(double c, double dt, double h) {
   return (c * dt) / h;
 }
 
-template <typename T>
-__device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
-template <typename T>
-__device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
 __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
 __device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
-
 __device__ __forceinline__ float vfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double vfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -116,10 +111,22 @@ __device__ __forceinline__ T minmod4(T a, T b, T c, T d) {
 }
 
 template <typename T>
-__device__ __forceinline__ T pp_theta(T u_up, T u) {
-  T den = u_up - u;
-  T t = den > T(0) ? u_up / den : T(0);
-  return vmin(vmax(t, T(0)), T(1));
+__device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T u_plus, T u_minus) {
+  // theta = U^UP / (U^UP - U) on each side whose half-update is negative
+  // (zero when the denominator is not positive), clamped to [0, 1]; the
+  // flux moves toward the upwind value f0 by 1 - min(theta+, theta-).
+  T th = T(1);
+  if (u_plus < T(0)) {
+    const T up = f0 - tz * f0;
+    const T den = up - u_plus;
+    th = den > T(0) ? vmin(vmax(up / den, T(0)), T(1)) : T(0);
+  }
+  if (u_minus < T(0)) {
+    const T up = vfma(tz, f0, fp1);
+    const T den = up - u_minus;
+    th = vmin(th, den > T(0) ? vmin(vmax(up / den, T(0)), T(1)) : T(0));
+  }
+  return th * phib + (T(1) - th) * f0;
 }
 
 // Interface flux at the face between processing positions m and m+1
@@ -127,7 +134,7 @@ __device__ __forceinline__ T pp_theta(T u_up, T u) {
 // r_{m-2}..r_{m+2} (fifth order).  d_m and DM_{m-1/2} come from the
 // previous face; d_{m+1} and DM_{m+1/2} are returned for the next one.
 template <typename T, int ORDER, int LIM>
-__device__ __forceinline__ T face_flux(const T* q, const T* w, T z, T alpha, T& d_m, T& dm_prev) {
+__device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha, T& d_m, T& dm_prev) {
   constexpr int o = (ORDER == 7) ? 1 : 0;  // offset of the MP stencil in q
   T phi = w[0] * q[0];
 #pragma unroll
@@ -139,8 +146,7 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T z, T alpha, T& 
     // App. A steps 4-7 (the early accept of step 3 is implied: a value
     // strictly between f_i and f* already lies in [f^min, f^max])
     const T d_new = vfma(T(-2), fp1, f0 + fp2);
-    const T dm_new = minmod4(vfma(T(4), d_m, -d_new), vfma(T(4), d_new, -d_m),
-                             d_m, d_new);
+    const T dm_new = minmod4(vfma(T(4), d_m, -d_new), vfma(T(4), d_new, -d_m), d_m, d_new);
     const T slope = f0 - fm1;
     const T f_ul = vfma(alpha, slope, f0);
     const T f_md = vfma(T(-0.5), dm_new, T(0.5) * (f0 + fp1));
@@ -152,85 +158,593 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T z, T alpha, T& 
     dm_prev = dm_new;
     if constexpr (LIM == SLMPP_LIM_MPP) {
       // PP limiter, Sec. 2.1.1: keep both half-updates non-negative
-      const T tz = z + z;
       const T u_plus = vfma(-tz, phib, f0);
       const T u_minus = vfma(tz, phib, fp1);
-      if (u_plus < T(0) || u_minus < T(0)) {
-        T th = T(1);
-        if (u_plus < T(0)) th = pp_theta(f0 - tz * f0, u_plus);
-        if (u_minus < T(0)) th = vmin(th, pp_theta(vfma(tz, f0, fp1), u_minus));
-        phib = th * phib + (T(1) - th) * f0;
-      }
+      if (vmin(u_plus, u_minus) < T(0)) phib = pp_limit(phib, f0, fp1, tz, u_plus, u_minus);
     }
     return phib;
   }
 }
 
-template <int MODE>
-__device__ __forceinline__ int row_index(int r, int n, int G) {
-  if constexpr (MODE == READ_DIRECT) {
-    return r + G;
-  } else if constexpr (MODE == READ_WRAP) {
-    r %= n;
-    if (r < 0) r += n;
-    return r + G;
-  } else {
-    return min(max(r, -G), n + G - 1) + G;
-  }
-}
+enum : int32_t { READ_DIRECT = 0, READ_SAFE = 1 };
 
-// Process positions [m0, m1) of one pencil whose input column starts at
-// col (stride pitch) and whose output column starts at out.
-template <typename T, int ORDER, int LIM, int MODE>
-__device__ void sweep_segment(const T* __restrict__ col, T* __restrict__ out,
-                              const ColParam<T>& cp, int n, int G, int pitch, int m0, int m1,
-                              T alpha) {
+// Advance cells m0 .. m0+cnt-1 of one pencil (processing order).  `col`
+// points at physical cell 0 of the pencil in the LDS tile; consecutive
+// cells are `stride` elements apart and G ghost cells exist on both sides.
+// READ_DIRECT assumes every read stays within the ghost cells; READ_SAFE
+// wraps (periodic) or clamps onto the zero ghost cells (outflow).  With
+// RC > 0 the segment length is RC and the results stay in out[]; with
+// RC == 0 they are written to `ocol` (same geometry as col, no ghosts).
+template <typename T, int ORDER, int LIM, int MODE, int RC>
+__device__ __forceinline__ void advance(const T* __restrict__ col, int stride, int n, int G,
+                                        int periodic, const PencilEntry<T>& e, int m0, int cnt,
+                                        T alpha, T* out, T* __restrict__ ocol) {
   constexpr int H = (ORDER == 7) ? 3 : 2;  // window r_{m-H}..r_{m+H}
   constexpr int WIN = 2 * H + 1;
   T w[ORDER];
 #pragma unroll
-  for (int k = 0; k < ORDER; ++k) w[k] = cp.w[k];
-  const T z = cp.z;
-  const int dir = cp.dir;
-  int r = cp.base + dir * (m0 - 1 - H);  // physical row of r_{m0-1-H}
+  for (int k = 0; k < ORDER; ++k) w[k] = e.w[k];
+  const T z = e.z;
+  const T tz = z + z;
+  const int dir = e.dir;
+  int r = e.base + dir * (m0 - 1 - H);  // physical cell of r_{m0-1-H}
+  const T* ptr = col + r * stride;      // READ_DIRECT walks a pointer
+  const int step = dir * stride;
+  auto fetch = [&]() -> T {
+    T v;
+    if constexpr (MODE == READ_DIRECT) {
+      v = *ptr;
+      ptr += step;
+    } else {
+      int rr = r;
+      if (periodic) {
+        rr %= n;
+        if (rr < 0) rr += n;
+      } else {
+        rr = min(max(rr, -G), n + G - 1);  // ghost cells are zero
+      }
+      v = col[rr * stride];
+      r += dir;
+    }
+    return v;
+  };
   T q[WIN];
 #pragma unroll
-  for (int k = 0; k < WIN; ++k) {
-    q[k] = col[row_index<MODE>(r, n, G) * pitch];
-    r += dir;
-  }
-  // carried MP quantities for the face m0-1/2 (upwind cell m0-1):
-  // d_{m0-1} and DM_{m0-3/2}
+  for (int k = 0; k < WIN; ++k) q[k] = fetch();
   constexpr int o = (ORDER == 7) ? 1 : 0;
-  T d_prev = vfma(T(-2), q[o + 1], q[o] + q[o + 2]);     // d_{m0-2}
-  T d_m = vfma(T(-2), q[o + 2], q[o + 1] + q[o + 3]);    // d_{m0-1}
-  T dm_prev = minmod4(vfma(T(4), d_prev, -d_m), vfma(T(4), d_m, -d_prev),
-                      d_prev, d_m);
-  T f_left = face_flux<T, ORDER, LIM>(q, w, z, alpha, d_m, dm_prev);
-  int orow = (dir > 0) ? m0 : (n - 1 - m0);
-  for (int m = m0; m < m1; ++m) {
+  T d_prev = vfma(T(-2), q[o + 1], q[o] + q[o + 2]);   // d_{m0-2}
+  T d_m = vfma(T(-2), q[o + 2], q[o + 1] + q[o + 3]);  // d_{m0-1}
+  T dm_prev = minmod4(vfma(T(4), d_prev, -d_m), vfma(T(4), d_m, -d_prev), d_prev, d_m);
+  T f_left = face_flux<T, ORDER, LIM>(q, w, tz, alpha, d_m, dm_prev);
+  if constexpr (RC > 0) {
 #pragma unroll
-    for (int k = 0; k < WIN - 1; ++k) q[k] = q[k + 1];
-    q[WIN - 1] = col[row_index<MODE>(r, n, G) * pitch];
-    r += dir;
-    const T f_right = face_flux<T, ORDER, LIM>(q, w, z, alpha, d_m, dm_prev);
-    const T cell = q[H];  // r_m
-    out[orow * pitch] = vfma(-z, f_right - f_left, cell);
-    f_left = f_right;
-    orow += dir;
+    for (int k = 0; k < RC; ++k) {
+#pragma unroll
+      for (int j = 0; j < WIN - 1; ++j) q[j] = q[j + 1];
+      q[WIN - 1] = fetch();
+      const T f_right = face_flux<T, ORDER, LIM>(q, w, tz, alpha, d_m, dm_prev);
+      out[k] = vfma(-z, f_right - f_left, q[H]);
+      f_left = f_right;
+    }
+  } else {
+    T* optr = ocol + ((dir > 0) ? m0 : (n - 1 - m0)) * stride;
+    for (int k = 0; k < cnt; ++k) {
+#pragma unroll
+      for (int j = 0; j < WIN - 1; ++j) q[j] = q[j + 1];
+      q[WIN - 1] = fetch();
+      const T f_right = face_flux<T, ORDER, LIM>(q, w, tz, alpha, d_m, dm_prev);
+      *optr = vfma(-z, f_right - f_left, q[H]);
+      optr += step;
+      f_left = f_right;
+    }
+  }
+}
+
+// 16-byte vectors as native clang vector types (kept in registers)
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  using type = vf4;
+  static constexpr int N = 4;
+};
+template <>
+struct Vec<double> {
+  using type = vd2;
+  static constexpr int N = 2;
+};
+
+// scatter / gather the components of a 16-byte vector to / from
+// consecutive elements (component access keeps the vector in registers)
+__device__ __forceinline__ void put(float* d, const vf4& v) {
+  d[0] = v.x;
+  d[1] = v.y;
+  d[2] = v.z;
+  d[3] = v.w;
+}
+__device__ __forceinline__ void put(double* d, const vd2& v) {
+  d[0] = v.x;
+  d[1] = v.y;
+}
+__device__ __forceinline__ void get(const float* s, vf4& v) {
+  v.x = s[0];
+  v.y = s[1];
+  v.z = s[2];
+  v.w = s[3];
+}
+__device__ __forceinline__ void get(const double* s, vd2& v) {
+  v.x = s[0];
+  v.y = s[1];
+}
+
+// a / b for non-negative 64-bit values, in 32-bit arithmetic when both fit
+__device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
+  if (((a | b) >> 31) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
+  return a / b;
+}
+
+// LDS tile layouts.  Strided axis: row-major [cell][pencil] with pitch W
+// (a tile row is W consecutive elements of f; lanes of a wave read W
+// different pencils of one row, so every bank is distinct).  Contiguous
+// axis: pencil-major [pencil][cell] with an odd pitch (W pencils are W*n
+// consecutive elements of f; lanes reading cell r of W pencils hit
+// distinct banks).  Both layouts carry G ghost cells before and after each
+// pencil.
+// RC: cells per thread (0: runtime segment length).  WT: pencils per tile
+// as a compile-time constant (0: runtime), which turns the thread -> (pencil,
+// segment) and vector -> (row, column) maps into shifts and multiplies.
+template <typename T, int ORDER, int LIM, int RC, int WT>
+__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
+                                                    const PencilEntry<T>* __restrict__ table) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::N;
+  const int n = a.n, G = pl.G, P = pl.pitch;
+  const int W = WT > 0 ? WT : pl.W;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const bool periodic = a.bc == SLMPP_BC_PERIODIC;
+  const bool contiguous = a.inner == 1;
+  // element offset of ghost-extended cell g (0 <= g < n+2G) of pencil jj
+  // in the tile: contiguous jj*P + g, strided g*W + jj
+  const int cstride = contiguous ? 1 : W;  // between cells of a pencil
+  const int pstride = contiguous ? P : 1;  // between pencils
+  const int tile_elems = contiguous ? W * P : (n + 2 * G) * W;
+  T* tile = reinterpret_cast<T*>(smem);
+  const size_t tile_bytes = ((size_t)tile_elems * sizeof(T) + 15) & ~(size_t)15;
+  PencilEntry<T>* ent = reinterpret_cast<PencilEntry<T>*>(smem + tile_bytes);
+  T* tout = reinterpret_cast<T*>(ent + W);  // RC == 0 only: tile_elems
+  T* f = reinterpret_cast<T*>(a.f);
+  const T alpha = (T)a.alpha;
+
+  const int64_t p0 = (int64_t)blockIdx.x * W;
+  const int wv = (int)min<int64_t>(W, a.npen - p0);
+  const bool block = !contiguous && (a.inner % W == 0);
+  int64_t gbase = 0, o0 = 0, j0 = 0;
+  if (contiguous) {
+    gbase = p0 * n;
+  } else if (block) {
+    o0 = udiv(p0, a.inner);
+    j0 = p0 - o0 * a.inner;
+    gbase = o0 * (int64_t)n * a.inner + j0;
+  }
+
+  // ---- per-pencil table entry ------------------------------------------
+  int need_safe = 0;
+  for (int jj = tid; jj < W; jj += nthr) {
+    if (jj < wv) {
+      const int64_t p = p0 + jj;
+      int64_t o, j;
+      if (contiguous) {
+        o = p;
+        j = 0;
+      } else if (block) {
+        o = o0;
+        j = j0 + jj;
+      } else {
+        o = udiv(p, a.inner);
+        j = p - o * a.inner;
+      }
+      const int64_t idx = a.cmode == SPEED_FROM_VELOCITY ? udiv(j, a.vdiv) % a.nvl : udiv(o, a.xdiv);
+      const PencilEntry<T>* src = table + idx;
+      ent[jj] = *src;
+      need_safe |= src->absN > a.nfast;
+    } else {
+      ent[jj].z = T(0);
+      ent[jj].base = 0;
+      ent[jj].dir = 1;
+      ent[jj].absN = 0;
+    }
+  }
+
+  // ---- stream the tile in: global -> LDS ------------------------------------
+  // Loads are issued in batches of KB vectors per thread before any of them
+  // is written to LDS, so each thread keeps KB requests in flight.
+  constexpr int KB = 6;
+  const bool vec_strided = block && (W % VN) == 0 && (a.inner % VN) == 0 && (gbase % VN) == 0 &&
+                           (nthr % (W / VN)) == 0;
+  if (contiguous) {
+    const int total = wv * n;
+    if ((n % VN) == 0) {
+      // vector e4 holds cells i..i+VN-1 of pencil jj (n % VN == 0: never split)
+      const int nvec = total / VN;
+      const int stepE = nthr * VN;
+      const int dj = stepE / n, di = stepE - dj * n;
+      int jj = (tid * VN) / n, i = tid * VN - jj * n;
+      const V* src = reinterpret_cast<const V*>(f + gbase);
+      for (int b0 = tid; b0 < nvec; b0 += KB * nthr) {
+        V buf[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (b0 + k * nthr < nvec) buf[k] = src[b0 + k * nthr];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          if (b0 + k * nthr < nvec) {
+            put(tile + jj * P + G + i, buf[k]);
+            i += di;
+            jj += dj;
+            if (i >= n) {
+              i -= n;
+              ++jj;
+            }
+          }
+        }
+      }
+    } else {
+      for (int e2 = tid; e2 < total; e2 += nthr) {
+        const int jj = e2 / n, i = e2 - jj * n;
+        tile[jj * P + G + i] = f[gbase + e2];
+      }
+    }
+  } else if (vec_strided) {
+    const int cpr = W / VN;  // vectors per row; nthr % cpr == 0
+    const int c = tid % cpr;
+    const int di = nthr / cpr;
+    const int i0 = tid / cpr;
+    const T* gp = f + gbase + (int64_t)i0 * a.inner + c * VN;
+    const int64_t gstep = (int64_t)di * a.inner;
+    for (int ib = i0; ib < n; ib += KB * di, gp += KB * gstep) {
+      V buf[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (ib + k * di < n) buf[k] = *reinterpret_cast<const V*>(gp + k * gstep);
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (ib + k * di < n)
+          *reinterpret_cast<V*>(tile + (ib + k * di + G) * W + c * VN) = buf[k];
+    }
+  } else {
+    // generic strided tile: thread -> fixed pencil column, rows stepped
+    const int jj = tid % W;
+    if (jj < wv && (nthr % W) == 0) {
+      const int64_t p = p0 + jj;
+      const int64_t o = udiv(p, a.inner);
+      const T* gp = f + o * (int64_t)n * a.inner + (p - o * a.inner);
+      const int di = nthr / W;
+      for (int ib = tid / W; ib < n; ib += KB * di) {
+        T buf[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (ib + k * di < n) buf[k] = gp[(int64_t)(ib + k * di) * a.inner];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (ib + k * di < n) tile[(ib + k * di + G) * W + jj] = buf[k];
+      }
+    }
+  }
+  // zero ghost cells (outflow); periodic images are copied after the barrier
+  if (!periodic) {
+    for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
+      const int g = e2 / W, jj = e2 - g * W;
+      tile[jj * pstride + (g < G ? g : n + g) * cstride] = T(0);
+    }
+  }
+  const bool safe = __syncthreads_or(need_safe) != 0;
+  if (periodic && G > 0) {
+    for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
+      const int g = e2 / W, jj = e2 - g * W;
+      const int pr = g < G ? g - G : n + (g - G);  // physical cell of the ghost
+      int sp = pr < 0 ? pr + n : (pr >= n ? pr - n : pr);
+      if (G > n) {  // pencils shorter than the ghost width
+        sp = pr % n;
+        if (sp < 0) sp += n;
+      }
+      tile[jj * pstride + (g < G ? g : n + g) * cstride] = tile[jj * pstride + (sp + G) * cstride];
+    }
+    __syncthreads();
+  }
+
+  // ---- compute: thread -> (pencil jj, segment s) -------------------------
+  const int jj = tid % W;
+  const int s = tid / W;
+  const PencilEntry<T> e = ent[jj];
+  const T* col = tile + jj * pstride + G * cstride;  // physical cell 0
+  if constexpr (RC > 0) {
+    T out[RC > 0 ? RC : 1];
+    const int m0 = s * RC;
+    const bool act = jj < wv && m0 < n;
+    if (act) {
+      if (!safe)
+        advance<T, ORDER, LIM, READ_DIRECT, RC>(col, cstride, n, G, periodic, e, m0, RC, alpha,
+                                                out, nullptr);
+      else
+        advance<T, ORDER, LIM, READ_SAFE, RC>(col, cstride, n, G, periodic, e, m0, RC, alpha, out,
+                                              nullptr);
+    }
+    __syncthreads();
+    if (act) {
+      T* op = tile + jj * pstride + (G + ((e.dir > 0) ? m0 : (n - 1 - m0))) * cstride;
+      const int ostep = e.dir * cstride;
+#pragma unroll
+      for (int k = 0; k < RC; ++k) {
+        *op = out[k];
+        op += ostep;
+      }
+    }
+  } else {
+    const int S = nthr / W;
+    const int R = (n + S - 1) / S;
+    const int m0 = s * R;
+    const int cnt = min(n, m0 + R) - m0;
+    if (jj < wv && cnt > 0) {
+      T* ocol = tout + jj * pstride + G * cstride;
+      if (!safe)
+        advance<T, ORDER, LIM, READ_DIRECT, 0>(col, cstride, n, G, periodic, e, m0, cnt, alpha,
+                                               nullptr, ocol);
+      else
+        advance<T, ORDER, LIM, READ_SAFE, 0>(col, cstride, n, G, periodic, e, m0, cnt, alpha,
+                                             nullptr, ocol);
+    }
+  }
+  __syncthreads();
+  const T* res = RC > 0 ? tile : tout;  // same geometry as the tile
+
+  // ---- stream the tile out in place ---------------------------------------
+  if (contiguous) {
+    const int total = wv * n;
+    if ((n % VN) == 0) {
+      const int nvec = total / VN;
+      const int stepE = nthr * VN;
+      const int dj = stepE / n, di = stepE - dj * n;
+      int c = (tid * VN) / n, i = tid * VN - c * n;
+      V* dst = reinterpret_cast<V*>(f + gbase);
+      for (int b0 = tid; b0 < nvec; b0 += KB * nthr) {
+        V buf[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          if (b0 + k * nthr < nvec) {
+            get(res + c * P + G + i, buf[k]);
+            i += di;
+            c += dj;
+            if (i >= n) {
+              i -= n;
+              ++c;
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (b0 + k * nthr < nvec) dst[b0 + k * nthr] = buf[k];
+      }
+    } else {
+      for (int e2 = tid; e2 < total; e2 += nthr) {
+        const int c = e2 / n, i = e2 - c * n;
+        f[gbase + e2] = res[c * P + G + i];
+      }
+    }
+  } else if (vec_strided) {
+    const int cpr = W / VN;
+    const int c = tid % cpr;
+    const int di = nthr / cpr;
+    const int i0 = tid / cpr;
+    T* gp = f + gbase + (int64_t)i0 * a.inner + c * VN;
+    const int64_t gstep = (int64_t)di * a.inner;
+    for (int ib = i0; ib < n; ib += KB * di, gp += KB * gstep) {
+      V buf[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (ib + k * di < n) buf[k] = *reinterpret_cast<const V*>(res + (ib + k * di + G) * W + c * VN);
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (ib + k * di < n) *reinterpret_cast<V*>(gp + k * gstep) = buf[k];
+    }
+  } else {
+    const int c = tid % W;
+    if (c < wv && (nthr % W) == 0) {
+      const int64_t p = p0 + c;
+      const int64_t o = udiv(p, a.inner);
+      T* gp = f + o * (int64_t)n * a.inner + (p - o * a.inner);
+      for (int i = tid / W; i < n; i += nthr / W) gp[(int64_t)i * a.inner] = res[(i + G) * W + c];
+    }
+  }
+}
+
+// Fast path: persistent workgroups over whole tiles with software prefetch.
+// Each thread owns RC cells of one pencil and, for the data movement, RC
+// elements of the tile (RC/VN vectors at fixed offsets, the same for every
+// tile), so the loads of the next tile can be issued into registers before
+// the current tile is computed.  Requirements checked on the host: SL-MPP,
+// W divides `inner` (strided) or inner == 1 (contiguous), RC divides n,
+// VN divides RC (and n when contiguous), and all pencil / cell counts of a
+// block fit in 32 bits.
+template <typename T, int ORDER, int RC, int WT, bool CONTIG>
+__global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan pl,
+                                                         const PencilEntry<T>* __restrict__ table) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::N;
+  constexpr int NV = RC / VN;  // vectors per thread and tile
+  constexpr int W = WT;
+  static_assert(RC % VN == 0, "segment length must be a multiple of the vector width");
+  const int n = a.n, G = pl.G, P = pl.pitch;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int S = nthr / W;
+  const bool periodic = a.bc == SLMPP_BC_PERIODIC;
+  const int cstride = CONTIG ? 1 : W;
+  const int pstride = CONTIG ? P : 1;
+  const int tile_elems = CONTIG ? W * P : (n + 2 * G) * W;
+  T* tile = reinterpret_cast<T*>(smem);
+  const size_t tile_bytes = ((size_t)tile_elems * sizeof(T) + 15) & ~(size_t)15;
+  PencilEntry<T>* ent = reinterpret_cast<PencilEntry<T>*>(smem + tile_bytes);
+  T* f = reinterpret_cast<T*>(a.f);
+  const T alpha = (T)a.alpha;
+  const uint32_t inner = (uint32_t)a.inner;
+
+  // per-thread element map of the data movement (identical for every tile)
+  int loff[NV];       // LDS element offset of vector k
+  int64_t goff0;      // global element offset of vector 0 relative to the tile
+  int64_t gstep;      // between consecutive vectors of the thread
+  int vlim[NV];       // vector k exists when the tile has more than vlim[k] valid pencils
+  if constexpr (CONTIG) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = VN * (tid + k * nthr);
+      const int pj = e / n;
+      loff[k] = pj * P + G + (e - pj * n);
+      vlim[k] = pj;
+    }
+    goff0 = (int64_t)VN * tid;
+    gstep = (int64_t)VN * nthr;
+  } else {
+    constexpr int cpr = W / VN;
+    const int c = tid % cpr, i0 = tid / cpr;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      loff[k] = (i0 + k * S * VN + G) * W + c * VN;
+      vlim[k] = c * VN;
+    }
+    goff0 = (int64_t)i0 * inner + c * VN;
+    gstep = (int64_t)S * VN * inner;
+  }
+  // zero ghost cells once: interior writes never touch them
+  if (!periodic) {
+    for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
+      const int g = e2 / W, c = e2 - g * W;
+      tile[c * pstride + (g < G ? g : n + g) * cstride] = T(0);
+    }
+  }
+  const int jj = tid % W;
+  const int s = tid / W;
+  const int m0 = s * RC;
+
+  auto tile_base = [&](int64_t t, int& wv) -> int64_t {
+    const int64_t p0 = t * W;
+    wv = (int)min<int64_t>(W, a.npen - p0);
+    if constexpr (CONTIG) {
+      return p0 * n;
+    } else {
+      const uint32_t o0 = (uint32_t)p0 / inner;
+      const uint32_t j0 = (uint32_t)p0 - o0 * inner;
+      return (int64_t)o0 * n * inner + j0;
+    }
+  };
+
+  V pf[NV];
+  int64_t t = blockIdx.x;
+  int wv_next = 0;
+  int64_t gb_next = 0;
+  if (t < pl.tiles) {
+    gb_next = tile_base(t, wv_next);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (vlim[k] < wv_next) pf[k] = *reinterpret_cast<const V*>(f + gb_next + goff0 + k * gstep);
+  }
+  for (; t < pl.tiles; t += gridDim.x) {
+    const int wv = wv_next;
+    const int64_t gbase = gb_next;
+    const int64_t p0 = t * W;
+    // ---- pencil entries of this tile ----
+    int need_safe = 0;
+    if (tid < W) {
+      if (tid < wv) {
+        uint32_t idx;
+        if constexpr (CONTIG) {
+          const uint32_t o = (uint32_t)(p0 + tid);
+          idx = a.cmode == SPEED_FROM_VELOCITY ? 0u : o / (uint32_t)a.xdiv;
+        } else {
+          const uint32_t o0 = (uint32_t)p0 / inner;
+          const uint32_t j = (uint32_t)p0 - o0 * inner + tid;
+          idx = a.cmode == SPEED_FROM_VELOCITY ? (j / (uint32_t)a.vdiv) % (uint32_t)a.nvl
+                                               : o0 / (uint32_t)a.xdiv;
+        }
+        const PencilEntry<T>* src = table + idx;
+        ent[tid] = *src;
+        need_safe = src->absN > a.nfast;
+      } else {
+        ent[tid].z = T(0);
+        ent[tid].base = 0;
+        ent[tid].dir = 1;
+        ent[tid].absN = 0;
+      }
+    }
+    // ---- prefetched data -> LDS ----
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (vlim[k] < wv) put(tile + loff[k], pf[k]);
+    const bool safe = __syncthreads_or(need_safe) != 0;
+    if (periodic) {
+      for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
+        const int g = e2 / W, c = e2 - g * W;
+        const int pr = g < G ? g - G : n + (g - G);
+        int sp = pr < 0 ? pr + n : (pr >= n ? pr - n : pr);
+        if (G > n) {
+          sp = pr % n;
+          if (sp < 0) sp += n;
+        }
+        tile[c * pstride + (g < G ? g : n + g) * cstride] = tile[c * pstride + (sp + G) * cstride];
+      }
+      __syncthreads();
+    }
+    // ---- issue the loads of the next tile ----
+    if (t + gridDim.x < pl.tiles) {
+      gb_next = tile_base(t + gridDim.x, wv_next);
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (vlim[k] < wv_next) pf[k] = *reinterpret_cast<const V*>(f + gb_next + goff0 + k * gstep);
+    }
+    // ---- compute ----
+    const PencilEntry<T> e = ent[jj];
+    const bool act = jj < wv;
+    T out[RC];
+    const T* col = tile + jj * pstride + G * cstride;
+    if (act) {
+      if (!safe)
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_DIRECT, RC>(col, cstride, n, G, periodic, e, m0, RC,
+                                                          alpha, out, nullptr);
+      else
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, RC>(col, cstride, n, G, periodic, e, m0, RC,
+                                                        alpha, out, nullptr);
+    }
+    __syncthreads();
+    if (act) {
+      T* op = tile + jj * pstride + (G + ((e.dir > 0) ? m0 : (n - 1 - m0))) * cstride;
+      const int ostep = e.dir * cstride;
+#pragma unroll
+      for (int k = 0; k < RC; ++k) {
+        *op = out[k];
+        op += ostep;
+      }
+    }
+    __syncthreads();
+    // ---- stream the results out ----
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      if (vlim[k] < wv) {
+        V v;
+        get(tile + loff[k], v);
+        *reinterpret_cast<V*>(f + gbase + goff0 + k * gstep) = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <typename T, int ORDER>
-__device__ void column_params(const SweepArgs& a, int64_t p, ColParam<T>& cp) {
-  double c;
-  if (a.cmode == SPEED_FROM_VELOCITY) {
-    const int64_t j = p % a.inner;
-    const int64_t jv = (j / a.vdiv) % a.nvl;
-    c = cell_center(a.vlo, a.dv, jv);
-  } else {
-    c = a.accel[(p / a.inner) / a.xdiv];
-  }
+__global__ void pencil_table_kernel(SweepArgs a, PencilEntry<T>* __restrict__ tab, int count) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const double c = a.cmode == SPEED_FROM_VELOCITY ? cell_center(a.vlo, a.dv, idx) : a.accel[idx];
   const double xi = departure(c, a.dt, a.h);
   const int n = a.n;
   double zeta;
@@ -253,12 +767,11 @@ __device__ void column_params(const SweepArgs& a, int64_t p, ColParam<T>& cp) {
   }
   const bool mirror = zeta < 0.0;
   const double az = mirror ? -zeta : zeta;
-  cp.dir = mirror ? -1 : 1;
-  cp.base = (int32_t)((mirror ? (int64_t)(n - 1) : 0) - N);
-  const int64_t aN = N < 0 ? -N : N;
-  cp.mode = aN <= a.nfast ? READ_DIRECT : (a.bc == SLMPP_BC_PERIODIC ? READ_WRAP : READ_CLAMP);
-  cp.z = (T)az;
-  cp.valid = 1;
+  PencilEntry<T> e{};
+  e.dir = mirror ? -1 : 1;
+  e.base = (int32_t)((mirror ? (int64_t)(n - 1) : 0) - N);
+  e.absN = (int32_t)(N < 0 ? -N : N);
+  e.z = (T)az;
 #pragma unroll
   for (int k = 0; k < ORDER; ++k) {
     double acc = 0.0;
@@ -272,193 +785,183 @@ __device__ void column_params(const SweepArgs& a, int64_t p, ColParam<T>& cp) {
       }
       acc = acc * az + fr.num / fr.den;
     }
-    cp.w[k] = (T)acc;
+    e.w[k] = (T)acc;
   }
+  tab[idx] = e;
 }
 
-template <typename T, int ORDER, int LIM>
-__global__ void __launch_bounds__(256) sweep_tile_kernel(SweepArgs a, SweepPlan pl) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n = a.n, W = pl.W, G = pl.G, pitch = pl.pitch;
-  const int rows = n + 2 * G;
-  T* tin = reinterpret_cast<T*>(smem);
-  T* tout = tin + (size_t)rows * pitch;
-  const size_t cp_off = ((size_t)(rows + n) * pitch * sizeof(T) + 15) & ~(size_t)15;
-  ColParam<T>* cps = reinterpret_cast<ColParam<T>*>(smem + cp_off);
-  T* f = reinterpret_cast<T*>(a.f);
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  const T alpha = (T)a.alpha;
-  const bool contiguous = (a.inner == 1);
-
-  for (int64_t tile = blockIdx.x; tile < pl.tiles; tile += gridDim.x) {
-    const int64_t p0 = tile * W;
-    const int wv = (int)((a.npen - p0) < W ? (a.npen - p0) : W);  // valid pencils
-    // ---- stream the tile in: global -> LDS rows [G, G+n) ----
-    if (contiguous) {
-      const int64_t gbase = p0 * n;
-      const int total = wv * n;
-      int jj = tid / n, i = tid - (tid / n) * n;
-      const int sj = nthr / n, si = nthr - sj * n;
-      for (int e = tid; e < total; e += nthr) {
-        tin[(i + G) * pitch + jj] = f[gbase + e];
-        i += si;
-        jj += sj;
-        if (i >= n) { i -= n; ++jj; }
-      }
-    } else {
-      const int jj = tid % W;
-      const int64_t p = p0 + jj;
-      if (jj < wv) {
-        const int64_t o = p / a.inner;
-        const int64_t gb = o * (int64_t)n * a.inner + (p - o * a.inner);
-        for (int i = tid / W; i < n; i += nthr / W) tin[(i + G) * pitch + jj] = f[gb + (int64_t)i * a.inner];
-      }
-    }
-    // ---- ghost rows: periodic images or zeros ----
-    for (int e = tid; e < 2 * G * W; e += nthr) {
-      const int g = e / W, jj = e - g * W;
-      const int gr = g < G ? g - G : n + (g - G);  // physical row of the ghost
-      const int lrow = g < G ? g : n + g;          // LDS row
-      T v = T(0);
-      if (a.bc == SLMPP_BC_PERIODIC && jj < wv) {
-        int src = gr % n;
-        if (src < 0) src += n;
-        const int64_t p = p0 + jj;
-        const int64_t o = p / a.inner;
-        v = f[o * (int64_t)n * a.inner + (int64_t)src * a.inner + (p - o * a.inner)];
-      }
-      tin[lrow * pitch + jj] = v;
-    }
-    // ---- per-pencil shift, direction and CSL weights ----
-    for (int jj = tid; jj < W; jj += nthr) {
-      if (jj < wv) {
-        column_params<T, ORDER>(a, p0 + jj, cps[jj]);
-      } else {
-        ColParam<T> c{};
-        c.dir = 1;
-        c.mode = READ_DIRECT;
-        c.valid = 0;
-        cps[jj] = c;
-      }
-    }
-    __syncthreads();
-    // ---- compute: thread -> (pencil jj, segment s) ----
-    {
-      const int jj = tid % W;
-      const int s = tid / W;
-      const int S = nthr / W;
-      const int R = (n + S - 1) / S;
-      const int m0 = s * R;
-      const int m1 = min(n, m0 + R);
-      const ColParam<T> cp = cps[jj];
-      if (cp.valid && m0 < m1) {
-        const T* col = tin + jj;
-        T* out = tout + jj;
-        if (cp.mode == READ_DIRECT)
-          sweep_segment<T, ORDER, LIM, READ_DIRECT>(col, out, cp, n, G, pitch, m0, m1, alpha);
-        else if (cp.mode == READ_WRAP)
-          sweep_segment<T, ORDER, LIM, READ_WRAP>(col, out, cp, n, G, pitch, m0, m1, alpha);
-        else
-          sweep_segment<T, ORDER, LIM, READ_CLAMP>(col, out, cp, n, G, pitch, m0, m1, alpha);
-      }
-    }
-    __syncthreads();
-    // ---- stream the tile out in place ----
-    if (contiguous) {
-      const int64_t gbase = p0 * n;
-      const int total = wv * n;
-      int jj = tid / n, i = tid - (tid / n) * n;
-      const int sj = nthr / n, si = nthr - sj * n;
-      for (int e = tid; e < total; e += nthr) {
-        f[gbase + e] = tout[i * pitch + jj];
-        i += si;
-        jj += sj;
-        if (i >= n) { i -= n; ++jj; }
-      }
-    } else {
-      const int jj = tid % W;
-      const int64_t p = p0 + jj;
-      if (jj < wv) {
-        const int64_t o = p / a.inner;
-        const int64_t gb = o * (int64_t)n * a.inner + (p - o * a.inner);
-        for (int i = tid / W; i < n; i += nthr / W) f[gb + (int64_t)i * a.inner] = tout[i * pitch + jj];
-      }
-    }
-    __syncthreads();
-  }
+size_t entry_bytes(int dtype) {
+  return dtype == SLMPP_F64 ? sizeof(PencilEntry<double>) : sizeof(PencilEntry<float>);
 }
 
-template <typename T, int ORDER, int LIM>
-hipError_t launch_t(const SweepArgs& a, const SweepPlan& p, hipStream_t s) {
-  if (p.tiles <= 0) return hipSuccess;
-  auto kern = sweep_tile_kernel<T, ORDER, LIM>;
+template <typename T, int ORDER, int LIM, int RC, int WT>
+hipError_t launch_k(const SweepArgs& a, const SweepPlan& p, const void* table, hipStream_t s) {
+  auto kern = sweep_kernel<T, ORDER, LIM, RC, WT>;
   if (p.lds_bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)p.lds_bytes);
     if (e != hipSuccess) return e;
   }
-  const int64_t grid = std::min<int64_t>(p.tiles, (int64_t)1 << 30);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(p.threads), p.lds_bytes, s, a, p);
+  hipLaunchKernelGGL(kern, dim3((unsigned)p.tiles), dim3(p.threads), p.lds_bytes, s, a, p,
+                     reinterpret_cast<const PencilEntry<T>*>(table));
   return hipGetLastError();
 }
 
-template <typename T, int ORDER>
-hipError_t launch_o(int limiter, const SweepArgs& a, const SweepPlan& p, hipStream_t s) {
-  switch (limiter) {
-    case SLMPP_LIM_NONE: return launch_t<T, ORDER, SLMPP_LIM_NONE>(a, p, s);
-    case SLMPP_LIM_MP: return launch_t<T, ORDER, SLMPP_LIM_MP>(a, p, s);
-    default: return launch_t<T, ORDER, SLMPP_LIM_MPP>(a, p, s);
+template <typename T, int ORDER, int RC, int WT, bool CONTIG>
+hipError_t launch_fast(const SweepArgs& a, const SweepPlan& p, const void* table, hipStream_t s) {
+  auto kern = sweep_fast_kernel<T, ORDER, RC, WT, CONTIG>;
+  if (p.lds_bytes > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)p.lds_bytes);
+    if (e != hipSuccess) return e;
   }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(kern), p.threads, p.lds_bytes);
+  if (e != hipSuccess) return e;
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t slots = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
+  const int64_t grid = std::min<int64_t>(p.tiles, slots);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(p.threads), p.lds_bytes, s, a, p,
+                     reinterpret_cast<const PencilEntry<T>*>(table));
+  return hipGetLastError();
 }
 
-size_t colparam_bytes(int dtype) {
-  return dtype == SLMPP_F64 ? sizeof(ColParam<double>) : sizeof(ColParam<float>);
+template <typename T, int ORDER, int RC>
+hipError_t launch_w(const SweepArgs& a, const SweepPlan& p, const void* table, hipStream_t s) {
+  if (p.fast) {
+    if (a.inner == 1) return launch_fast<T, ORDER, RC, 64, true>(a, p, table, s);
+    switch (p.W) {
+      case 64: return launch_fast<T, ORDER, RC, 64, false>(a, p, table, s);
+      case 48: return launch_fast<T, ORDER, RC, 48, false>(a, p, table, s);
+      case 32: return launch_fast<T, ORDER, RC, 32, false>(a, p, table, s);
+      default: break;
+    }
+  }
+  return launch_k<T, ORDER, SLMPP_LIM_MPP, RC, 0>(a, p, table, s);
+}
+
+template <typename T, int ORDER, int LIM>
+hipError_t launch_r(const SweepArgs& a, const SweepPlan& p, const void* table, hipStream_t s) {
+  if constexpr (LIM == SLMPP_LIM_MPP) {
+    switch (p.R) {
+      case 12: return launch_w<T, ORDER, 12>(a, p, table, s);
+      case 16: return launch_w<T, ORDER, 16>(a, p, table, s);
+      case 24: return launch_w<T, ORDER, 24>(a, p, table, s);
+      default: break;
+    }
+  }
+  SweepPlan g = p;
+  g.R = 0;
+  return launch_k<T, ORDER, LIM, 0, 0>(a, g, table, s);
+}
+
+template <typename T, int ORDER>
+hipError_t launch_o(int limiter, const SweepArgs& a, const SweepPlan& p, void* table, int count,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((pencil_table_kernel<T, ORDER>), dim3((count + 127) / 128), dim3(128), 0, s,
+                     a, reinterpret_cast<PencilEntry<T>*>(table), count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.tiles <= 0) return e;
+  switch (limiter) {
+    case SLMPP_LIM_NONE: return launch_r<T, ORDER, SLMPP_LIM_NONE>(a, p, table, s);
+    case SLMPP_LIM_MP: return launch_r<T, ORDER, SLMPP_LIM_MP>(a, p, table, s);
+    default: return launch_r<T, ORDER, SLMPP_LIM_MPP>(a, p, table, s);
+  }
 }
 
 }  // namespace
 
-SweepPlan plan_sweep(int dtype, int order, int32_t n, int64_t npen, int64_t inner, int32_t nfast,
-                     int W_override, int S_override) {
+size_t pencil_table_bytes(int dtype, int64_t count) { return entry_bytes(dtype) * (size_t)count; }
+
+SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen, int64_t inner,
+                     int32_t nfast, int W_override, int S_override) {
   SweepPlan p{};
   const size_t es = dtype == SLMPP_F64 ? 8 : 4;
   const int gh = order == 7 ? 4 : 3;
   p.G = gh + nfast;
-  const size_t budget = 80 * 1024;  // keeps two workgroups per CU at the largest tiles
-  auto lds = [&](int W) {
-    const size_t tiles = ((size_t)(2 * n + 2 * p.G) * (W + 1) * es + 15) & ~(size_t)15;
-    return tiles + (size_t)W * colparam_bytes(dtype);
+  const bool contiguous = inner == 1;
+  auto pitch_of = [&](int W) {
+    (void)W;
+    int P = n + 2 * p.G;  // contiguous: pencil-major rows, odd pitch
+    if ((P & 1) == 0) ++P;
+    return contiguous ? P : W;
   };
-  int W = 64;
+  auto lds = [&](int W, bool regs) {
+    const size_t elems = contiguous ? (size_t)W * pitch_of(W) : (size_t)(n + 2 * p.G) * W;
+    size_t b = (elems * es + 15) & ~(size_t)15;
+    b += (size_t)W * entry_bytes(dtype);
+    if (!regs) b += elems * es;
+    return b;
+  };
+  // W: pencils per tile.  Strided tiles should not straddle a block of
+  // `inner` pencils, so W divides inner when a divisor in the list exists.
+  int W = 0;
   if (W_override > 0) {
     W = W_override;
+  } else if (contiguous) {
+    W = 64;
   } else {
-    while (W > 1 && lds(W) > budget) W /= 2;
+    for (int c : {64, 48, 32, 16}) {
+      if (inner % c == 0) {
+        W = c;
+        break;
+      }
+    }
+    if (W == 0) W = 64;
   }
-  (void)inner;
-  int S;
+  while (W > 1 && lds(W, false) > 96 * 1024) W /= 2;
+  // R: cells per thread; a compile-time length when it divides n
+  int R = 0;
   if (S_override > 0) {
-    S = S_override;
+    const int S = S_override;
+    R = (n % S == 0 && (n / S == 12 || n / S == 16 || n / S == 24)) ? n / S : 0;
+    p.S = S;
   } else {
-    S = std::max(1, 256 / W);
-    S = std::min(S, std::max(1, n / 8));  // at least ~8 cells per segment
+    for (int c : {12, 16, 24}) {
+      if (n % c == 0 && W * (n / c) <= 256) {
+        R = c;
+        break;
+      }
+    }
+    p.S = R ? n / R : std::max(1, std::min(256 / std::max(1, W), std::max(1, n / 8)));
   }
-  S = std::max(1, std::min(S, 256 / std::max(1, W)));
+  p.S = std::max(1, std::min(p.S, 256 / std::max(1, W)));
+  if (R && p.S * R != n) R = 0;
+  if (limiter != SLMPP_LIM_MPP) R = 0;  // compile-time segments exist for SL-MPP only
+  p.R = R;
   p.W = W;
-  p.S = S;
-  p.threads = W * S;
-  p.pitch = W + 1;
-  p.lds_bytes = lds(W);
+  p.threads = W * p.S;
+  p.pitch = pitch_of(W);
+  p.lds_bytes = lds(W, R > 0);
   p.tiles = (npen + W - 1) / W;
+  // the persistent prefetching kernel (see sweep_fast_kernel)
+  const int vn = dtype == SLMPP_F64 ? 2 : 4;
+  const bool fits32 = npen < ((int64_t)1 << 31) && inner < ((int64_t)1 << 31) &&
+                      (int64_t)n * W < ((int64_t)1 << 24);
+  p.fast = R > 0 && R % vn == 0 && fits32 && W_override == 0 &&
+           (contiguous ? (W == 64 && n % vn == 0) : (inner % W == 0 && inner % vn == 0 &&
+                                                     (W == 64 || W == 48 || W == 32)));
+  if (p.fast) p.lds_bytes = lds(W, true);
   return p;
 }
 
 hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a, const SweepPlan& p,
-                        hipStream_t s) {
+                        void* table, int64_t table_count, hipStream_t s) {
+  const int count = (int)table_count;
   if (dtype == SLMPP_F64)
-    return order == 7 ? launch_o<double, 7>(limiter, a, p, s) : launch_o<double, 5>(limiter, a, p, s);
-  return order == 7 ? launch_o<float, 7>(limiter, a, p, s) : launch_o<float, 5>(limiter, a, p, s);
+    return order == 7 ? launch_o<double, 7>(limiter, a, p, table, count, s)
+                      : launch_o<double, 5>(limiter, a, p, table, count, s);
+  return order == 7 ? launch_o<float, 7>(limiter, a, p, table, count, s)
+                    : launch_o<float, 5>(limiter, a, p, table, count, s);
 }
 
 int32_t max_shift_velocity(double vlo, double dv, int32_t nvl, double dt, double h, int32_t n,

@@ -246,3 +246,61 @@ def test_error_paths(S):
         ctx.step(float("inf"), 1)
     assert np.array_equal(ctx.get_f(), f_before)
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# shapes that select the compile-time tile kernels (48-cell axes: tiles of
+# 64 or 48 pencils, 12 cells per thread; 16-cell axes: 16 cells per thread)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("order", [5, 7])
+def test_fast_tiles_2d2v_48(S, storage, order):
+    spec = W.landau_3d3v(n=48, D=2, order=order, amp=0.2)
+    say(f"case landau_2d2v 48^2x48^2 order={order} storage={storage}")
+    got, ref, diag = _run_pair(S, spec, storage, 2)
+    err = l1rel(got, ref)
+    say(f"  L1 rel = {err:.3e}")
+    assert err <= (1e-13 if storage == 0 else 1e-6)
+    assert diag["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_fast_tiles_3d3v_16(S, storage):
+    spec = W.jeans_3d3v(n=16, order=5)
+    spec["dt"] *= 4.0  # larger shifts in x
+    say(f"case jeans_3d3v 16^3x16^3 storage={storage}")
+    got, ref, _ = _run_pair(S, spec, storage, 1)
+    err = l1rel(got, ref)
+    say(f"  L1 rel = {err:.3e}")
+    assert err <= (1e-13 if storage == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_fast_tiles_random_sweeps_48(S, storage):
+    """Every axis of a 2D2V 48^4 grid with random data and shifts up to
+    three cells in both directions, one sweep at a time."""
+    spec = W.spec(2, [48, 48], [48, 48], [0.0, 0.0], [1.0, 1.3], [-2.0, -3.0], [2.0, 2.5],
+                  order=7, limiter=W.LIM_MPP)
+    grid = O.make_grid(spec)
+    f0 = _stored(W.random_field(grid.shape, 4242), storage)
+    nxs = 48 * 48
+    acc = W.random_accel(nxs, 2, 4243, scale=1.0)
+    import torch
+    for axis in range(4):
+        for dt in (0.013, -0.031):
+            say(f"case fast random axis={axis} dt={dt} storage={storage}")
+            ctx = _ctx(S, spec, storage, f0)
+            ref = f0.copy()
+            if axis < 2:
+                ctx.advect_x(axis, dt)
+                O.advect_x(grid, ref, axis, dt)
+            else:
+                l = axis - 2
+                hv = (spec["v_hi"][l] - spec["v_lo"][l]) / 48
+                comp = acc[l * nxs:(l + 1) * nxs] * 3.0 * hv / abs(dt)
+                ctx.advect_v(l, dt, torch.tensor(comp, dtype=torch.float64, device="cuda"))
+                O.advect_v(grid, ref, l, dt, comp)
+            got = ctx.get_f()
+            ctx.close()
+            tol = 1e-13 if storage == 0 else 64 * 2.0 ** -24
+            assert np.abs(got - ref).max() / np.abs(ref).max() <= tol, (axis, dt)
