@@ -102,9 +102,12 @@ typedef struct {
 } slmpp_diag_out;
 
 /* Per-kernel-class timing gathered with HIP events on the context stream. */
-#define SLMPP_TIMING_CLASSES 4 /* 0: sweeps along a strided axis,
+#define SLMPP_TIMING_CLASSES 6 /* 0: sweeps along a strided axis, tiles of
+                                     64 pencils,
                                   1: sweeps along the contiguous axis,
-                                  2: velocity moment, 3: Poisson + force   */
+                                  2: velocity moment, 3: Poisson + force,
+                                  4: sweeps along a strided axis, other tiles,
+                                  5: per-pencil shift / weight tables     */
 typedef struct {
   int64_t launches[SLMPP_TIMING_CLASSES];
   double total_ms[SLMPP_TIMING_CLASSES];  /* summed kernel durations       */

@@ -271,9 +271,13 @@ struct slmpp_ctx {
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
     const double cells = (double)ncell;
-    hipError_t e = tic(inner == 1 ? 1 : 0, 2.0 * cells * esize(), cells);
     const int64_t tcount = a < D ? d.nv[a] : nxs;
-    if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), tcount, stream);
+    hipError_t e = tic(5, 0.0, 0.0);
+    if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, s, table(), tcount, stream);
+    if (e == hipSuccess) e = toc();
+    const int cls = inner == 1 ? 1 : (p.W == 64 ? 0 : 4);
+    if (e == hipSuccess) e = tic(cls, 2.0 * cells * esize(), cells);
+    if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
     if (e == hipSuccess) e = toc();
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     return SLMPP_OK;

@@ -47,10 +47,12 @@ struct SweepPlan {
 SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen, int64_t inner,
                      int32_t nfast, int W_override = 0, int S_override = 0);
 
-// Enqueue the pencil table (table_count entries, one per distinct speed)
-// and the sweep.  `table` is device scratch of pencil_table_bytes().
+// Enqueue the pencil table (table_count entries, one per distinct speed;
+// `table` is device scratch of pencil_table_bytes()), then the sweep.
+hipError_t launch_pencil_table(int dtype, int order, const SweepArgs& a, void* table,
+                               int64_t table_count, hipStream_t s);
 hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a,
-                        const SweepPlan& p, void* table, int64_t table_count, hipStream_t s);
+                        const SweepPlan& p, const void* table, hipStream_t s);
 size_t pencil_table_bytes(int dtype, int64_t count);
 
 // Integer-shift bound of a sweep along x_l: max |N| over the velocity

@@ -865,17 +865,21 @@ hipError_t launch_r(const SweepArgs& a, const SweepPlan& p, const void* table, h
 }
 
 template <typename T, int ORDER>
-hipError_t launch_o(int limiter, const SweepArgs& a, const SweepPlan& p, void* table, int count,
+hipError_t launch_o(int limiter, const SweepArgs& a, const SweepPlan& p, const void* table,
                     hipStream_t s) {
-  hipLaunchKernelGGL((pencil_table_kernel<T, ORDER>), dim3((count + 127) / 128), dim3(128), 0, s,
-                     a, reinterpret_cast<PencilEntry<T>*>(table), count);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || p.tiles <= 0) return e;
+  if (p.tiles <= 0) return hipSuccess;
   switch (limiter) {
     case SLMPP_LIM_NONE: return launch_r<T, ORDER, SLMPP_LIM_NONE>(a, p, table, s);
     case SLMPP_LIM_MP: return launch_r<T, ORDER, SLMPP_LIM_MP>(a, p, table, s);
     default: return launch_r<T, ORDER, SLMPP_LIM_MPP>(a, p, table, s);
   }
+}
+
+template <typename T, int ORDER>
+hipError_t launch_table_t(const SweepArgs& a, void* table, int count, hipStream_t s) {
+  hipLaunchKernelGGL((pencil_table_kernel<T, ORDER>), dim3((count + 127) / 128), dim3(128), 0, s,
+                     a, reinterpret_cast<PencilEntry<T>*>(table), count);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -954,14 +958,23 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
   return p;
 }
 
-hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a, const SweepPlan& p,
-                        void* table, int64_t table_count, hipStream_t s) {
+hipError_t launch_pencil_table(int dtype, int order, const SweepArgs& a, void* table,
+                               int64_t table_count, hipStream_t s) {
   const int count = (int)table_count;
   if (dtype == SLMPP_F64)
-    return order == 7 ? launch_o<double, 7>(limiter, a, p, table, count, s)
-                      : launch_o<double, 5>(limiter, a, p, table, count, s);
-  return order == 7 ? launch_o<float, 7>(limiter, a, p, table, count, s)
-                    : launch_o<float, 5>(limiter, a, p, table, count, s);
+    return order == 7 ? launch_table_t<double, 7>(a, table, count, s)
+                      : launch_table_t<double, 5>(a, table, count, s);
+  return order == 7 ? launch_table_t<float, 7>(a, table, count, s)
+                    : launch_table_t<float, 5>(a, table, count, s);
+}
+
+hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a, const SweepPlan& p,
+                        const void* table, hipStream_t s) {
+  if (dtype == SLMPP_F64)
+    return order == 7 ? launch_o<double, 7>(limiter, a, p, table, s)
+                      : launch_o<double, 5>(limiter, a, p, table, s);
+  return order == 7 ? launch_o<float, 7>(limiter, a, p, table, s)
+                    : launch_o<float, 5>(limiter, a, p, table, s);
 }
 
 int32_t max_shift_velocity(double vlo, double dv, int32_t nvl, double dt, double h, int32_t n,
