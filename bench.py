@@ -42,6 +42,8 @@ def workload(name, dtype):
         return W.landau_nl_1d1v()
     if name == "landau_1d1v":
         return W.landau_1d1v()
+    if name == "ensemble":
+        return None
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -91,6 +93,101 @@ def cpu_baseline(spec_fn, n_sample):
     }
 
 
+def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ensemble]"):
+    """The batched ensemble: 256 independent runs of uneven sizes advanced
+    together by the captured step graph, tile widths autotuned."""
+    import numpy as np
+    import torch
+
+    from paper_1702_08521_amd import slmpp, workloads as W
+
+    specs = W.ensemble()
+    storage = slmpp.F32 if dtype == "f32" else slmpp.F64
+    stream = torch.cuda.Stream()
+
+    def make(st):
+        b = slmpp.Batch([slmpp.make_desc(s, st) for s in specs], [s["dt"] for s in specs],
+                        stream=stream)
+        for r, s in enumerate(specs):
+            sx, gv = W.separable_factors(s)
+            b.init_separable(r, sx, gv)
+        return b
+
+    cells = [int(np.prod(s["nx"][:s["D"]])) * int(np.prod(s["nv"][:s["D"]])) for s in specs]
+    updates = sum(c * 3 * s["D"] for c, s in zip(cells, specs))  # cell-updates per step
+    es = 4 if storage == slmpp.F32 else 8
+    # algorithmic HBM bytes of a step: read + write f per sweep, one read for the moment
+    step_bytes = sum(c * es * (2 * 3 * s["D"] + 1) for c, s in zip(cells, specs))
+    b = make(storage)
+    t0 = time.perf_counter()
+    b.autotune(None)
+    tune_s = time.perf_counter() - t0
+    widths = {}
+    for r, s in enumerate(specs):
+        for a in range(2 * s["D"]):
+            w = b.tile_width(r, a)
+            widths[w] = widths.get(w, 0) + 1
+    if warmup:
+        b.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    b.step(steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / steps
+    ev0.record(stream)
+    b.step_eager(steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    eager_ms = ev0.elapsed_time(ev1) / steps
+    log(f"{log_prefix} {len(specs)} runs, {sum(cells):.3e} cells, graph {graph_ms:.3f} ms/step, "
+        f"eager {eager_ms:.3f} ms/step, autotune {tune_s:.2f} s")
+    out = {
+        "runs": len(specs),
+        "cells": sum(cells),
+        "cell_updates_per_step": updates,
+        "steps": steps,
+        "graph_ms_per_step": round(graph_ms, 4),
+        "eager_ms_per_step": round(eager_ms, 4),
+        "cell_updates_per_s": updates / (graph_ms * 1e-3),
+        "step_GB_s": round(step_bytes / (graph_ms * 1e-3) / 1e9, 1),
+        "step_bytes": step_bytes,
+        "autotune_s": round(tune_s, 3),
+        "tile_widths": {str(k): v for k, v in sorted(widths.items())},
+    }
+    if compare_fp64 and storage == slmpp.F32:
+        # the same ensemble in FP64 storage from the same start, for the error
+        # of FP32 storage and the FP64 rate on the same GPU
+        n_cmp = 100
+        b32 = make(slmpp.F32)
+        b64 = make(slmpp.F64)
+        b32.step(n_cmp)
+        b64.autotune(None)
+        b64.step(n_cmp)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        b64.step(n_cmp)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms64 = ev0.elapsed_time(ev1) / n_cmp
+        b32.step(n_cmp)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for r in range(len(specs)):
+            a32, a64 = b32.get_f(r), b64.get_f(r)
+            worst = max(worst, float(np.abs(a32 - a64).sum() / np.abs(a64).sum()))
+        out["fp64_same_ensemble"] = {"graph_ms_per_step": round(ms64, 4),
+                                     "cell_updates_per_s": updates / (ms64 * 1e-3)}
+        out["fp32_vs_fp64_L1_rel_max_over_runs"] = worst
+        out["fp32_vs_fp64_steps"] = 2 * n_cmp
+        b32.close()
+        b64.close()
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +197,10 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps of the whole ensemble in its cpu_baseline (--workload ensemble)")
+    ap.add_argument("--ensemble-steps", type=int, default=100,
+                    help="steps of the batched ensemble reported in detail.ensemble (0: skip)")
     ap.add_argument("--fp64-compare", type=int, default=3,
                     help="steps of the same workload in FP64 storage for the FP32-vs-FP64 line (0: skip)")
     args = ap.parse_args()
@@ -115,6 +216,8 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.workload == "ensemble":
+        return ensemble_main(args)
     spec = workload(args.workload, args.dtype)
     storage = slmpp.F32 if args.dtype == "f32" else slmpp.F64
     D = spec["D"]
@@ -227,6 +330,10 @@ def main():
         del ctx64
         torch.cuda.empty_cache()
 
+    if args.ensemble_steps > 0 and storage == slmpp.F32:
+        out["detail"]["ensemble"] = ensemble_leg(args.ensemble_steps, 5, "f32", compare_fp64=True)
+        torch.cuda.empty_cache()
+
     # reference: a plain streaming copy of 4 GiB with the library's copy kernel
     nbytes = 4 << 30
     src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -256,6 +363,59 @@ def main():
 
         out["cpu_baseline"] = cpu_baseline(spec_fn, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def ensemble_main(args):
+    """--workload ensemble: the batched form as the bench line."""
+    from paper_1702_08521_amd import workloads as W
+
+    ens = ensemble_leg(args.steps, args.warmup, args.dtype, compare_fp64=args.fp64_compare > 0)
+    es = 4 if args.dtype == "f32" else 8
+    achieved = ens["step_bytes"] / (ens["graph_ms_per_step"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": ens["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ens["graph_ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"ensemble of {ens['runs']} Landau-type runs (1D1V and 2D2V, "
+                               f"SL-MPP5/7 mixed, seed {W.ENSEMBLE_SEED}), "
+                               f"{args.dtype} f, graph-captured step",
+                   "cells": ens["cells"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole captured step (batch tables, sweeps, moment, Poisson)",
+                     "bytes_per_step": ens["step_bytes"], "element_bytes": es},
+        "detail": ens,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = ensemble_cpu_baseline(W.ensemble(), args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def ensemble_cpu_baseline(specs, steps):
+    """FP64 oracle: `steps` Strang steps of every run of the ensemble."""
+    import numpy as np
+
+    import oracle as O
+
+    runs = [O.Run(s) for s in specs]
+    t0 = time.perf_counter()
+    for run, s in zip(runs, specs):
+        run.step(s["dt"], steps)
+    dt = time.perf_counter() - t0
+    upd = steps * sum(int(np.prod(s["nx"][:s["D"]])) * int(np.prod(s["nv"][:s["D"]])) * 3 * s["D"]
+                      for s in specs)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": upd / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} Strang steps of all {len(specs)} ensemble runs, FP64, {dt:.2f} s"}
 
 
 if __name__ == "__main__":

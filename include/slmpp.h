@@ -218,6 +218,61 @@ slmpp_status slmpp_timing_read(slmpp_ctx* ctx, slmpp_timing* out);
 slmpp_status slmpp_copy_device(void* dst_dev, const void* src_dev, size_t bytes,
                                void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent runs (each with its own grid, order,
+ * dt and initial condition) advanced together.  Every phase of the Strang
+ * step (Eq. (splitting)) is one grouped launch over all runs -- pencil
+ * tables, then a persistent sweep kernel whose work items are tiles of the
+ * runs' pencils -- and the field solve is one batched moment launch plus
+ * one Poisson workgroup per run.  slmpp_batch_step replays the whole step
+ * as one captured HIP graph.
+ *
+ * Restrictions: all runs share the storage type; limiter SLMPP_LIM_MPP;
+ * at most 2048 spatial cells per run (the Poisson solve of a run works in
+ * the LDS of one workgroup); dt fixed per run at creation.
+ * ------------------------------------------------------------------------ */
+typedef struct slmpp_batch slmpp_batch;
+
+/* Device workspace bytes for an ensemble of nruns descriptions (0 when any
+ * description is invalid or the runs cannot form a batch). */
+size_t slmpp_batch_workspace_bytes(const slmpp_grid_desc* descs, int32_t nruns);
+
+/* Create an ensemble.  f_dev[r]: caller-owned device array of run r
+ * (16-byte aligned, prod(nx)*prod(nv) values of the storage type); dts[r]:
+ * the run's time step (finite).  work_dev: caller-owned workspace of at
+ * least slmpp_batch_workspace_bytes() bytes, 256-byte aligned. */
+slmpp_status slmpp_batch_create(const slmpp_grid_desc* descs, const double* dts, int32_t nruns,
+                                void* const* f_dev, void* work_dev, size_t work_bytes,
+                                void* hip_stream, slmpp_batch** out);
+slmpp_status slmpp_batch_destroy(slmpp_batch* b);
+/* Message of the last failing call on b; NULL: last failing create. */
+const char* slmpp_batch_last_error(const slmpp_batch* b);
+
+/* f_r(x, v) <- s(x) g1(v1) g2(v2) g3(v3) for run r (as slmpp_init_f_separable). */
+slmpp_status slmpp_batch_init_separable(slmpp_batch* b, int32_t run, const double* s_host,
+                                        const double* g1, const double* g2, const double* g3);
+
+/* Advance every run by nsteps steps of its own dt: the captured step graph
+ * is replayed nsteps times (captured on first use, re-captured after
+ * slmpp_batch_autotune).  The acceleration of each run is recomputed from
+ * f first when an init call changed f. */
+slmpp_status slmpp_batch_step(slmpp_batch* b, int32_t nsteps);
+/* The same launches enqueued directly on the stream, without the graph. */
+slmpp_status slmpp_batch_step_eager(slmpp_batch* b, int32_t nsteps);
+
+/* Copy run r's f to the host as doubles (n cells).  Synchronises. */
+slmpp_status slmpp_batch_get_f(slmpp_batch* b, int32_t run, double* f_host, int64_t n);
+
+/* Choose the tile width of every distinct pencil shape of the ensemble by
+ * timing the candidates (64, 32, 16, 8 pencils per 256-thread tile) on a
+ * scratch copy of a run's data.  cache_path (may be NULL) is a text file
+ * of "dtype order n inner W" lines: shapes found there are not re-timed,
+ * and new choices are appended.  Synchronises. */
+slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path);
+
+/* Tile width chosen for run r's sweep along array axis a (0..2D-1). */
+int32_t slmpp_batch_tile_width(const slmpp_batch* b, int32_t run, int32_t axis);
+
 #ifdef __cplusplus
 }
 #endif

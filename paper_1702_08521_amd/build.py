@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libslmpp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["sweep.hip", "field.hip", "api.hip"]
+SOURCES = ["sweep.hip", "field.hip", "batch.hip", "api.hip", "batch_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 ARCH = os.environ.get("SLMPP_OFFLOAD_ARCH", "gfx950")

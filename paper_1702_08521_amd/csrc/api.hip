@@ -73,9 +73,11 @@ Layout layout_of(const slmpp_grid_desc& d) {
   return L;
 }
 
-bool finite(double x) { return std::isfinite(x); }
+bool is_finite(double x) { return std::isfinite(x); }
 
-slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) {
+}  // namespace
+
+slmpp_status slmpp::check_grid_desc(const slmpp_grid_desc* d, std::string& msg) {
   if (!d) {
     msg = "desc is NULL";
     return SLMPP_ERR_INVALID;
@@ -109,7 +111,7 @@ slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) {
     msg = "flags must be 0";
     return SLMPP_ERR_INVALID;
   }
-  if (!finite(d->alpha) || !(d->alpha > 0.0) || !finite(d->kappa)) {
+  if (!is_finite(d->alpha) || !(d->alpha > 0.0) || !is_finite(d->kappa)) {
     msg = "alpha must be finite and > 0, kappa finite";
     return SLMPP_ERR_NONFINITE;
   }
@@ -119,8 +121,8 @@ slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) {
       msg = "every axis needs 1..4096 cells";
       return SLMPP_ERR_SHAPE;
     }
-    if (!finite(d->x_lo[l]) || !finite(d->x_hi[l]) || !finite(d->v_lo[l]) ||
-        !finite(d->v_hi[l])) {
+    if (!is_finite(d->x_lo[l]) || !is_finite(d->x_hi[l]) || !is_finite(d->v_lo[l]) ||
+        !is_finite(d->v_hi[l])) {
       msg = "domain bounds must be finite";
       return SLMPP_ERR_NONFINITE;
     }
@@ -138,6 +140,8 @@ slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) {
   return SLMPP_OK;
 }
 
+namespace {
+slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) { return check_grid_desc(d, msg); }
 }  // namespace
 
 struct slmpp_ctx {

@@ -1,0 +1,655 @@
+// Host runtime of batched ensembles (slmpp_batch_* in include/slmpp.h):
+// per-run workspace layout, grouped launch lists for every phase of the
+// Strang step, the captured step graph, and the tile-width autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "slmpp_internal.hpp"
+
+using namespace slmpp;
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct RunGeom {
+  int D;
+  int64_t dims[6];
+  int64_t nxs, nvs, ncell;
+  double hx[3], hv[3];
+};
+
+RunGeom geom_of(const slmpp_grid_desc& d) {
+  RunGeom g{};
+  g.D = d.D;
+  g.nxs = 1;
+  g.nvs = 1;
+  for (int l = 0; l < d.D; ++l) {
+    g.dims[l] = d.nx[l];
+    g.dims[d.D + l] = d.nv[l];
+    g.nxs *= d.nx[l];
+    g.nvs *= d.nv[l];
+    g.hx[l] = (d.x_hi[l] - d.x_lo[l]) / (double)d.nx[l];
+    g.hv[l] = (d.v_hi[l] - d.v_lo[l]) / (double)d.nv[l];
+  }
+  g.ncell = g.nxs * g.nvs;
+  return g;
+}
+
+// One phase of the step: a sweep along v_l (half step) or x_l (full step).
+struct SlotDef {
+  bool vel;
+  int l;
+  double frac;  // fraction of dt
+};
+
+std::vector<SlotDef> slot_defs(int Dmax, int& npre) {
+  std::vector<SlotDef> s;
+  for (int l = 0; l < Dmax; ++l) s.push_back({true, l, 0.5});
+  for (int l = Dmax - 1; l >= 0; --l) s.push_back({false, l, 1.0});
+  npre = (int)s.size();
+  for (int l = 0; l < Dmax; ++l) s.push_back({true, l, 0.5});
+  return s;
+}
+
+const int kCandidates[] = {64, 32, 16, 8};
+constexpr int kMinW = 8;
+
+struct Layout {
+  std::vector<size_t> rho, phi, acc, tab;
+  size_t runs, sweeps, items, mitems, scratch, stage, total;
+  int64_t max_sweeps, max_items, nmitems, stage_doubles;
+};
+
+Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
+  Layout L{};
+  const int n = (int)d.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  int Dmax = 1;
+  int64_t max_cells = 1, stage = 1;
+  L.max_items = 0;
+  L.nmitems = 0;
+  for (int r = 0; r < n; ++r) {
+    const RunGeom g = geom_of(d[r]);
+    Dmax = std::max(Dmax, g.D);
+    L.rho.push_back(take(8 * g.nxs));
+    L.phi.push_back(take(8 * g.nxs));
+    L.acc.push_back(take(8 * g.nxs * g.D));
+    int64_t maxnv = 1, sumnv = 0;
+    for (int l = 0; l < g.D; ++l) {
+      maxnv = std::max<int64_t>(maxnv, d[r].nv[l]);
+      sumnv += d[r].nv[l];
+    }
+    L.tab.push_back(take(pencil_table_bytes(SLMPP_F64, std::max(maxnv, g.nxs))));
+    // work items: every sweep of a step at the smallest tile width
+    for (int a = 0; a < 2 * g.D; ++a) {
+      const int64_t npen = g.ncell / g.dims[a];
+      L.max_items += (a >= g.D ? 2 : 1) * ((npen + kMinW - 1) / kMinW);
+    }
+    L.nmitems += g.nxs;
+    max_cells = std::max(max_cells, g.ncell);
+    stage = std::max(stage, g.nxs + sumnv);
+  }
+  L.max_sweeps = (int64_t)n * 3 * Dmax;
+  L.runs = take(sizeof(BatchRun) * n);
+  L.sweeps = take(sizeof(BatchSweep) * L.max_sweeps);
+  L.items = take(sizeof(BatchItem) * std::max<int64_t>(L.max_items, 1));
+  L.mitems = take(sizeof(int2) * std::max<int64_t>(L.nmitems, 1));
+  L.scratch = take(8 * max_cells);
+  L.stage_doubles = std::max<int64_t>(stage, std::min<int64_t>(max_cells, (int64_t)1 << 22));
+  L.stage = take(8 * L.stage_doubles);
+  L.total = off;
+  return L;
+}
+
+slmpp_status check_batch(const slmpp_grid_desc* descs, int32_t nruns, std::string& msg) {
+  if (!descs || nruns < 1) {
+    msg = "descs must be non-NULL and nruns >= 1";
+    return SLMPP_ERR_INVALID;
+  }
+  for (int r = 0; r < nruns; ++r) {
+    slmpp_status st = check_grid_desc(&descs[r], msg);
+    if (st != SLMPP_OK) {
+      msg = "run " + std::to_string(r) + ": " + msg;
+      return st;
+    }
+    if (descs[r].storage != descs[0].storage) {
+      msg = "all runs of a batch must share the storage type";
+      return SLMPP_ERR_INVALID;
+    }
+    if (descs[r].limiter != SLMPP_LIM_MPP) {
+      msg = "batched runs use the SL-MPP limiter";
+      return SLMPP_ERR_INVALID;
+    }
+    if (geom_of(descs[r]).nxs > kBatchMaxSpace) {
+      msg = "run " + std::to_string(r) + " has more than 2048 spatial cells";
+      return SLMPP_ERR_SHAPE;
+    }
+  }
+  return SLMPP_OK;
+}
+
+std::string shape_key(int dtype, int order, int64_t n, int64_t inner) {
+  std::ostringstream o;
+  o << (dtype == SLMPP_F64 ? "f64" : "f32") << ' ' << order << ' ' << n << ' ' << inner;
+  return o.str();
+}
+
+}  // namespace
+
+struct slmpp_batch {
+  int nruns = 0, dtype = SLMPP_F32, Dmax = 1, npre = 0;
+  hipStream_t stream = nullptr;
+  std::vector<slmpp_grid_desc> d;
+  std::vector<RunGeom> g;
+  std::vector<double> dt;
+  std::vector<void*> f;
+  char* work = nullptr;
+  size_t work_bytes = 0;
+  Layout lay{};
+  std::vector<SlotDef> slots;
+  struct SlotLaunch {
+    int first_sweep, nsweeps, first_item, nitems, max_count, grid;
+    size_t lds;
+  };
+  std::vector<SlotLaunch> launches;
+  std::vector<BatchSweep> sweeps;
+  std::vector<BatchItem> items;
+  std::vector<BatchRun> runs;
+  std::map<std::string, int> width;  // shape key -> tile width
+  std::vector<int> run_axis_width;   // run * 6 + axis
+  int max_nxs = 1;
+  size_t max_lds = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;  // private stream the step graph is captured on
+  bool field_valid = false;
+  std::string err;
+
+  slmpp_status fail(slmpp_status code, const std::string& m) {
+    err = m;
+    return code;
+  }
+  slmpp_status hip_fail(hipError_t e, const char* what) {
+    return fail(SLMPP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+  template <typename T>
+  T* at(size_t off) {
+    return reinterpret_cast<T*>(work + off);
+  }
+
+  // Sweep arguments of run r for slot s (nullptr-table entries filled in).
+  bool sweep_of(int r, const SlotDef& sd, SweepArgs& a, int64_t& count) const {
+    const RunGeom& G = g[r];
+    if (sd.l >= G.D) return false;
+    const int axis = sd.vel ? G.D + sd.l : sd.l;
+    const int nd = 2 * G.D;
+    int64_t inner = 1, outer = 1;
+    for (int k = axis + 1; k < nd; ++k) inner *= G.dims[k];
+    for (int k = 0; k < axis; ++k) outer *= G.dims[k];
+    a = SweepArgs{};
+    a.f = f[r];
+    a.npen = outer * inner;
+    a.inner = inner;
+    a.n = (int32_t)G.dims[axis];
+    a.dt = sd.frac * dt[r];
+    a.alpha = d[r].alpha;
+    if (!sd.vel) {
+      int64_t vdiv = 1;
+      for (int k = G.D + sd.l + 1; k < nd; ++k) vdiv *= G.dims[k];
+      a.cmode = SPEED_FROM_VELOCITY;
+      a.vdiv = vdiv;
+      a.nvl = (int32_t)d[r].nv[sd.l];
+      a.vlo = d[r].v_lo[sd.l];
+      a.dv = G.hv[sd.l];
+      a.h = G.hx[sd.l];
+      a.bc = d[r].x_bc;
+      a.xdiv = 1;
+      a.nfast = max_shift_velocity(a.vlo, a.dv, a.nvl, a.dt, a.h, a.n, a.bc);
+      count = d[r].nv[sd.l];
+    } else {
+      int64_t xdiv = 1;
+      for (int k = G.D; k < axis; ++k) xdiv *= G.dims[k];
+      a.cmode = SPEED_FROM_ACCEL;
+      a.accel = reinterpret_cast<const double*>(work + lay.acc[r]) + (int64_t)sd.l * G.nxs;
+      a.xdiv = xdiv;
+      a.vdiv = 1;
+      a.nvl = 1;
+      a.h = G.hv[sd.l];
+      a.bc = d[r].v_bc;
+      a.nfast = 4;
+      count = G.nxs;
+    }
+    return true;
+  }
+
+  int default_width(int order, const SweepArgs& a) const {
+    for (int W : kCandidates) {
+      SweepPlan p = plan_batch_sweep(dtype, order, a.n, a.npen, a.inner, a.nfast, W);
+      if (p.lds_bytes) return W;
+    }
+    return 0;
+  }
+
+  // Build the grouped launch lists from the current tile widths and upload.
+  slmpp_status build() {
+    sweeps.clear();
+    items.clear();
+    launches.clear();
+    run_axis_width.assign((size_t)nruns * 6, 0);
+    max_lds = 0;
+    for (size_t si = 0; si < slots.size(); ++si) {
+      SlotLaunch L{(int)sweeps.size(), 0, (int)items.size(), 0, 0, 1, 0};
+      for (int r = 0; r < nruns; ++r) {
+        SweepArgs a;
+        int64_t count = 0;
+        if (!sweep_of(r, slots[si], a, count)) continue;
+        const std::string key = shape_key(dtype, d[r].order, a.n, a.inner);
+        int W = width.count(key) ? width[key] : default_width(d[r].order, a);
+        SweepPlan p = W ? plan_batch_sweep(dtype, d[r].order, a.n, a.npen, a.inner, a.nfast, W)
+                        : SweepPlan{};
+        if (!p.lds_bytes)
+          return fail(SLMPP_ERR_SHAPE, "run " + std::to_string(r) + ": pencils of " +
+                                           std::to_string(a.n) + " cells do not fit a batch tile");
+        const int axis = slots[si].vel ? g[r].D + slots[si].l : slots[si].l;
+        run_axis_width[(size_t)r * 6 + axis] = W;
+        BatchSweep b{};
+        b.a = a;
+        b.p = p;
+        b.table = work + lay.tab[r];
+        b.order = d[r].order;
+        b.count = (int32_t)count;
+        const int sidx = (int)sweeps.size();
+        sweeps.push_back(b);
+        for (int64_t t = 0; t < p.tiles; ++t) items.push_back(BatchItem{sidx, 0, t});
+        L.max_count = std::max<int>(L.max_count, (int)count);
+        L.lds = std::max(L.lds, p.lds_bytes);
+        ++L.nsweeps;
+      }
+      L.nitems = (int)items.size() - L.first_item;
+      max_lds = std::max(max_lds, L.lds);
+      launches.push_back(L);
+    }
+    if ((int64_t)items.size() > lay.max_items || (int64_t)sweeps.size() > lay.max_sweeps)
+      return fail(SLMPP_ERR_WORKSPACE, "batch work lists exceed the workspace");
+    hipError_t e = prepare_batch_kernels(dtype, max_lds, max_nxs);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel attributes");
+    int n_cu = 0, dev = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    for (auto& L : launches) {
+      const int per_cu = batch_sweep_blocks_per_cu(dtype, L.lds);
+      L.grid = std::max(1, std::min(L.nitems, per_cu * std::max(n_cu, 1)));
+    }
+    e = hipMemcpyAsync(at<BatchSweep>(lay.sweeps), sweeps.data(), sizeof(BatchSweep) * sweeps.size(),
+                       hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !items.empty())
+      e = hipMemcpyAsync(at<BatchItem>(lay.items), items.data(), sizeof(BatchItem) * items.size(),
+                         hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "upload of batch work lists");
+    drop_graph();
+    return SLMPP_OK;
+  }
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+
+  hipError_t enqueue_slot(int si, hipStream_t s) {
+    const SlotLaunch& L = launches[si];
+    if (L.nsweeps == 0) return hipSuccess;
+    const BatchSweep* sw = at<BatchSweep>(lay.sweeps) + L.first_sweep;
+    hipError_t e = launch_batch_tables(dtype, sw, L.nsweeps, L.max_count, s);
+    if (e == hipSuccess)
+      e = launch_batch_sweeps(dtype, at<BatchSweep>(lay.sweeps), at<BatchItem>(lay.items) + L.first_item,
+                              L.nitems, L.lds, L.grid, s);
+    return e;
+  }
+
+  hipError_t enqueue_field(hipStream_t s) {
+    hipError_t e = launch_batch_moment(dtype, at<BatchRun>(lay.runs), at<int2>(lay.mitems),
+                                       (int)lay.nmitems, s);
+    if (e == hipSuccess) e = launch_batch_poisson(at<BatchRun>(lay.runs), nruns, max_nxs, s);
+    return e;
+  }
+
+  hipError_t enqueue_step(hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int si = 0; si < npre && e == hipSuccess; ++si) e = enqueue_slot(si, s);
+    if (e == hipSuccess) e = enqueue_field(s);
+    for (int si = npre; si < (int)slots.size() && e == hipSuccess; ++si) e = enqueue_slot(si, s);
+    return e;
+  }
+
+  slmpp_status ensure_field() {
+    if (field_valid) return SLMPP_OK;
+    hipError_t e = enqueue_field(stream);
+    if (e != hipSuccess) return hip_fail(e, "batch field");
+    field_valid = true;
+    return SLMPP_OK;
+  }
+};
+
+extern "C" {
+
+size_t slmpp_batch_workspace_bytes(const slmpp_grid_desc* descs, int32_t nruns) {
+  std::string msg;
+  if (check_batch(descs, nruns, msg) != SLMPP_OK) return 0;
+  return layout_of(std::vector<slmpp_grid_desc>(descs, descs + nruns)).total;
+}
+
+slmpp_status slmpp_batch_create(const slmpp_grid_desc* descs, const double* dts, int32_t nruns,
+                                void* const* f_dev, void* work_dev, size_t work_bytes,
+                                void* hip_stream, slmpp_batch** out) {
+  try {
+    if (!out) {
+      g_batch_error = "out is NULL";
+      return SLMPP_ERR_INVALID;
+    }
+    *out = nullptr;
+    std::string msg;
+    slmpp_status st = check_batch(descs, nruns, msg);
+    if (st != SLMPP_OK) {
+      g_batch_error = msg;
+      return st;
+    }
+    if (!dts || !f_dev || !work_dev) {
+      g_batch_error = "dts, f_dev and work_dev must be non-NULL";
+      return SLMPP_ERR_INVALID;
+    }
+    if (reinterpret_cast<uintptr_t>(work_dev) % 256) {
+      g_batch_error = "work_dev must be 256-byte aligned";
+      return SLMPP_ERR_INVALID;
+    }
+    for (int r = 0; r < nruns; ++r) {
+      if (!std::isfinite(dts[r])) {
+        g_batch_error = "dt of run " + std::to_string(r) + " is not finite";
+        return SLMPP_ERR_NONFINITE;
+      }
+      if (!f_dev[r] || reinterpret_cast<uintptr_t>(f_dev[r]) % 16) {
+        g_batch_error = "f_dev[" + std::to_string(r) + "] must be non-NULL and 16-byte aligned";
+        return SLMPP_ERR_INVALID;
+      }
+    }
+    std::vector<slmpp_grid_desc> dv(descs, descs + nruns);
+    Layout lay = layout_of(dv);
+    if (work_bytes < lay.total) {
+      g_batch_error = "workspace of " + std::to_string(work_bytes) + " bytes, need " +
+                      std::to_string(lay.total);
+      return SLMPP_ERR_WORKSPACE;
+    }
+    slmpp_batch* b = new slmpp_batch();
+    b->nruns = nruns;
+    b->dtype = descs[0].storage;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->d = dv;
+    b->dt.assign(dts, dts + nruns);
+    b->f.assign(f_dev, f_dev + nruns);
+    b->work = static_cast<char*>(work_dev);
+    b->work_bytes = work_bytes;
+    b->lay = lay;
+    std::vector<int2> mitems;
+    for (int r = 0; r < nruns; ++r) {
+      b->g.push_back(geom_of(dv[r]));
+      const RunGeom& G = b->g.back();
+      b->Dmax = std::max(b->Dmax, G.D);
+      b->max_nxs = std::max<int>(b->max_nxs, (int)G.nxs);
+      BatchRun R{};
+      R.f = f_dev[r];
+      R.rho = b->at<double>(lay.rho[r]);
+      R.phi = b->at<double>(lay.phi[r]);
+      R.accel = b->at<double>(lay.acc[r]);
+      R.nxs = G.nxs;
+      R.nvs = G.nvs;
+      R.dvol = 1.0;
+      for (int l = 0; l < 3; ++l) {
+        R.nx[l] = l < G.D ? dv[r].nx[l] : 1;
+        R.h[l] = l < G.D ? G.hx[l] : 1.0;
+      }
+      for (int l = 0; l < G.D; ++l) R.dvol *= G.hv[l];
+      R.kappa = dv[r].kappa;
+      R.D = G.D;
+      R.poisson_order = dv[r].poisson_order;
+      b->runs.push_back(R);
+      for (int64_t ix = 0; ix < G.nxs; ++ix) mitems.push_back(make_int2(r, (int)ix));
+    }
+    b->slots = slot_defs(b->Dmax, b->npre);
+    hipError_t e = hipMemcpyAsync(b->at<BatchRun>(lay.runs), b->runs.data(),
+                                  sizeof(BatchRun) * b->runs.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->at<int2>(lay.mitems), mitems.data(), sizeof(int2) * mitems.size(),
+                         hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+      g_batch_error = std::string("batch upload: ") + hipGetErrorString(e);
+      delete b;
+      return SLMPP_ERR_DEVICE;
+    }
+    st = b->build();
+    if (st != SLMPP_OK) {
+      g_batch_error = b->err;
+      delete b;
+      return st;
+    }
+    *out = b;
+    return SLMPP_OK;
+  } catch (const std::bad_alloc&) {
+    g_batch_error = "host allocation failed";
+    return SLMPP_ERR_DEVICE;
+  }
+}
+
+slmpp_status slmpp_batch_destroy(slmpp_batch* b) {
+  if (!b) return SLMPP_ERR_INVALID;
+  (void)hipStreamSynchronize(b->stream);
+  b->drop_graph();
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+  return SLMPP_OK;
+}
+
+const char* slmpp_batch_last_error(const slmpp_batch* b) {
+  return b ? b->err.c_str() : g_batch_error.c_str();
+}
+
+slmpp_status slmpp_batch_init_separable(slmpp_batch* b, int32_t run, const double* s_host,
+                                        const double* g1, const double* g2, const double* g3) {
+  if (!b) return SLMPP_ERR_INVALID;
+  if (run < 0 || run >= b->nruns) return b->fail(SLMPP_ERR_INVALID, "run index out of range");
+  const RunGeom& G = b->g[run];
+  const double* gv[3] = {g1, g2, g3};
+  if (!s_host) return b->fail(SLMPP_ERR_INVALID, "s_host is NULL");
+  for (int l = 0; l < G.D; ++l)
+    if (!gv[l]) return b->fail(SLMPP_ERR_INVALID, "a velocity factor is NULL");
+  double* st = b->at<double>(b->lay.stage);
+  hipError_t e = hipMemcpyAsync(st, s_host, 8 * G.nxs, hipMemcpyHostToDevice, b->stream);
+  const double* gd[3] = {nullptr, nullptr, nullptr};
+  int64_t off = G.nxs;
+  for (int l = 0; l < G.D && e == hipSuccess; ++l) {
+    gd[l] = st + off;
+    e = hipMemcpyAsync(st + off, gv[l], 8 * b->d[run].nv[l], hipMemcpyHostToDevice, b->stream);
+    off += b->d[run].nv[l];
+  }
+  if (e == hipSuccess)
+    e = launch_init_separable(b->dtype, b->f[run], st, gd[0], gd[1], gd[2], G.D, b->d[run].nv,
+                              G.nxs, G.nvs, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return b->hip_fail(e, "batch init");
+  b->field_valid = false;
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_batch_step(slmpp_batch* b, int32_t nsteps) {
+  if (!b) return SLMPP_ERR_INVALID;
+  if (nsteps < 1) return b->fail(SLMPP_ERR_INVALID, "nsteps must be >= 1");
+  slmpp_status st = b->ensure_field();
+  if (st != SLMPP_OK) return st;
+  if (!b->exec) {
+    // captured on a private stream (the caller's may be the null stream,
+    // which cannot be captured); replayed on the caller's stream
+    hipError_t e = hipSuccess;
+    if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return b->hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return b->hip_fail(e, "begin capture");
+    hipError_t el = b->enqueue_step(b->capture);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(b->capture, &gr);
+    if (el != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return b->hip_fail(el, "step capture");
+    }
+    if (e != hipSuccess) return b->hip_fail(e, "end capture");
+    b->graph = gr;
+    e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      b->drop_graph();
+      return b->hip_fail(e, "graph instantiate");
+    }
+  }
+  for (int32_t i = 0; i < nsteps; ++i) {
+    hipError_t e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "graph launch");
+  }
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_batch_step_eager(slmpp_batch* b, int32_t nsteps) {
+  if (!b) return SLMPP_ERR_INVALID;
+  if (nsteps < 1) return b->fail(SLMPP_ERR_INVALID, "nsteps must be >= 1");
+  slmpp_status st = b->ensure_field();
+  if (st != SLMPP_OK) return st;
+  for (int32_t i = 0; i < nsteps; ++i) {
+    hipError_t e = b->enqueue_step(b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "batch step");
+  }
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_batch_get_f(slmpp_batch* b, int32_t run, double* f_host, int64_t n) {
+  if (!b) return SLMPP_ERR_INVALID;
+  if (run < 0 || run >= b->nruns) return b->fail(SLMPP_ERR_INVALID, "run index out of range");
+  if (!f_host) return b->fail(SLMPP_ERR_INVALID, "f_host is NULL");
+  if (n != b->g[run].ncell) return b->fail(SLMPP_ERR_SHAPE, "n does not match the run's cells");
+  const size_t es = b->dtype == SLMPP_F64 ? 8 : 4;
+  const int64_t chunk = b->lay.stage_doubles;
+  double* st = b->at<double>(b->lay.stage);
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = std::min(chunk, n - off);
+    hipError_t e = launch_to_double(b->dtype, static_cast<const char*>(b->f[run]) + off * es, st, m,
+                                    b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(f_host + off, st, 8 * m, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "batch get_f");
+  }
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path) {
+  if (!b) return SLMPP_ERR_INVALID;
+  // candidates are timed with the runs' real speeds
+  slmpp_status fst = b->ensure_field();
+  if (fst != SLMPP_OK) return fst;
+  // known choices
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream is(line);
+      std::string dt;
+      int order = 0, W = 0;
+      int64_t n = 0, inner = 0;
+      if (is >> dt >> order >> n >> inner >> W) {
+        const int dtype = dt == "f64" ? SLMPP_F64 : SLMPP_F32;
+        b->width[shape_key(dtype, order, n, inner)] = W;
+      }
+    }
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return b->fail(SLMPP_ERR_DEVICE, "event create");
+  std::vector<std::string> fresh;
+  const size_t es = b->dtype == SLMPP_F64 ? 8 : 4;
+  slmpp_status result = SLMPP_OK;
+  for (size_t si = 0; si < b->slots.size() && result == SLMPP_OK; ++si) {
+    for (int r = 0; r < b->nruns && result == SLMPP_OK; ++r) {
+      SweepArgs a;
+      int64_t count = 0;
+      if (!b->sweep_of(r, b->slots[si], a, count)) continue;
+      const std::string key = shape_key(b->dtype, b->d[r].order, a.n, a.inner);
+      if (b->width.count(key)) continue;
+      // time the candidates on a scratch copy of run r
+      void* scratch = b->work + b->lay.scratch;
+      hipError_t e = hipMemcpyAsync(scratch, b->f[r], es * b->g[r].ncell, hipMemcpyDeviceToDevice,
+                                    b->stream);
+      a.f = scratch;
+      if (e == hipSuccess) e = launch_pencil_table(b->dtype, b->d[r].order, a, b->work + b->lay.tab[r],
+                                                   count, b->stream);
+      int bestW = 0;
+      float best = 1e30f;
+      for (int W : kCandidates) {
+        if (e != hipSuccess) break;
+        SweepPlan p = plan_batch_sweep(b->dtype, b->d[r].order, a.n, a.npen, a.inner, a.nfast, W);
+        if (!p.lds_bytes) continue;
+        e = launch_generic_sweep(b->dtype, b->d[r].order, a, p, b->work + b->lay.tab[r], b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+          e = launch_generic_sweep(b->dtype, b->d[r].order, a, p, b->work + b->lay.tab[r], b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best) {
+          best = ms;
+          bestW = W;
+        }
+      }
+      if (e != hipSuccess) {
+        result = b->hip_fail(e, "autotune");
+        break;
+      }
+      if (bestW) {
+        b->width[key] = bestW;
+        fresh.push_back(key + " " + std::to_string(bestW));
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result != SLMPP_OK) return result;
+  if (cache_path && !fresh.empty()) {
+    std::ofstream out(cache_path, std::ios::app);
+    for (const auto& l : fresh) out << l << '\n';
+  }
+  return b->build();
+}
+
+int32_t slmpp_batch_tile_width(const slmpp_batch* b, int32_t run, int32_t axis) {
+  if (!b || run < 0 || run >= b->nruns || axis < 0 || axis >= 2 * b->g[run].D) return 0;
+  return b->run_axis_width[(size_t)run * 6 + axis];
+}
+
+}  // extern "C"

@@ -5,10 +5,14 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "slmpp.h"
 
 namespace slmpp {
+
+// Validation of a grid description shared by single runs and ensembles.
+slmpp_status check_grid_desc(const slmpp_grid_desc* d, std::string& msg);
 
 // Speed of a pencil: from the velocity cell centre of the pencil (sweeps
 // along x_l) or from an acceleration array indexed by the spatial cell
@@ -59,6 +63,51 @@ size_t pencil_table_bytes(int dtype, int64_t count);
 // centres of axis l, with the same split as the kernels.
 int32_t max_shift_velocity(double vlo, double dv, int32_t nvl, double dt, double h, int32_t n,
                            int32_t bc);
+
+// ---- batched ensembles (many independent runs per launch) ----
+// One sweep of one run inside a grouped launch.
+struct BatchSweep {
+  SweepArgs a;
+  SweepPlan p;
+  void* table;    // the run's pencil-table scratch
+  int32_t order;  // 5 or 7
+  int32_t count;  // table entries
+};
+// One work item of a grouped sweep launch: tile `tile` of sweep `sweep`.
+struct BatchItem {
+  int32_t sweep;
+  int32_t pad;
+  int64_t tile;
+};
+// Field data of one run.
+struct BatchRun {
+  const void* f;
+  double* rho;
+  double* phi;
+  double* accel;
+  int64_t nxs, nvs;
+  int64_t nx[3];
+  double h[3];
+  double dvol;
+  double kappa;
+  int32_t D;
+  int32_t poisson_order;
+};
+hipError_t launch_batch_tables(int dtype, const BatchSweep* sweeps, int nsweeps, int max_count,
+                               hipStream_t s);
+hipError_t launch_batch_sweeps(int dtype, const BatchSweep* sweeps, const BatchItem* items,
+                               int nitems, size_t lds_bytes, int grid, hipStream_t s);
+int batch_sweep_blocks_per_cu(int dtype, size_t lds_bytes);
+SweepPlan plan_batch_sweep(int dtype, int order, int32_t n, int64_t npen, int64_t inner,
+                           int32_t nfast, int W);
+hipError_t launch_generic_sweep(int dtype, int order, const SweepArgs& a, const SweepPlan& p,
+                                const void* table, hipStream_t s);
+hipError_t launch_batch_moment(int dtype, const BatchRun* runs, const int2* items, int nitems,
+                               hipStream_t s);
+hipError_t launch_batch_poisson(const BatchRun* runs, int nruns, int max_nxs, hipStream_t s);
+// Kernel attributes for the LDS sizes of a batch (outside any graph capture).
+hipError_t prepare_batch_kernels(int dtype, size_t sweep_lds, int max_nxs);
+constexpr int kBatchMaxSpace = 2048;  // spatial cells per run (one-workgroup Poisson)
 
 // ---- field kernels (field.hip) ----
 hipError_t launch_moment(int dtype, const void* f, int64_t nxs, int64_t nvs, double dvol,

@@ -296,9 +296,9 @@ __device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
 // as a compile-time constant (0: runtime), which turns the thread -> (pencil,
 // segment) and vector -> (row, column) maps into shifts and multiplies.
 template <typename T, int ORDER, int LIM, int RC, int WT>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
-                                                    const PencilEntry<T>* __restrict__ table) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& pl,
+                                           const PencilEntry<T>* __restrict__ table,
+                                           int64_t tile_index, unsigned char* smem) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::N;
   const int n = a.n, G = pl.G, P = pl.pitch;
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
   T* f = reinterpret_cast<T*>(a.f);
   const T alpha = (T)a.alpha;
 
-  const int64_t p0 = (int64_t)blockIdx.x * W;
+  const int64_t p0 = tile_index * W;
   const int wv = (int)min<int64_t>(W, a.npen - p0);
   const bool block = !contiguous && (a.inner % W == 0);
   int64_t gbase = 0, o0 = 0, j0 = 0;
@@ -560,6 +560,13 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
   }
 }
 
+template <typename T, int ORDER, int LIM, int RC, int WT>
+__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
+                                                    const PencilEntry<T>* __restrict__ table) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sweep_tile<T, ORDER, LIM, RC, WT>(a, pl, table, (int64_t)blockIdx.x, smem);
+}
+
 // Fast path: persistent workgroups over whole tiles with software prefetch.
 // Each thread owns RC cells of one pencil and, for the data movement, RC
 // elements of the tile (RC/VN vectors at fixed offsets, the same for every
@@ -740,10 +747,9 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
   }
 }
 
+// Pencil-table entry for speed index idx (see PencilEntry).
 template <typename T, int ORDER>
-__global__ void pencil_table_kernel(SweepArgs a, PencilEntry<T>* __restrict__ tab, int count) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
+__device__ __forceinline__ PencilEntry<T> pencil_entry(const SweepArgs& a, int idx) {
   const double c = a.cmode == SPEED_FROM_VELOCITY ? cell_center(a.vlo, a.dv, idx) : a.accel[idx];
   const double xi = departure(c, a.dt, a.h);
   const int n = a.n;
@@ -787,7 +793,13 @@ __global__ void pencil_table_kernel(SweepArgs a, PencilEntry<T>* __restrict__ ta
     }
     e.w[k] = (T)acc;
   }
-  tab[idx] = e;
+  return e;
+}
+
+template <typename T, int ORDER>
+__global__ void pencil_table_kernel(SweepArgs a, PencilEntry<T>* __restrict__ tab, int count) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) tab[idx] = pencil_entry<T, ORDER>(a, idx);
 }
 
 size_t entry_bytes(int dtype) {
@@ -882,7 +894,122 @@ hipError_t launch_table_t(const SweepArgs& a, void* table, int count, hipStream_
   return hipGetLastError();
 }
 
+// ---- grouped launches over many independent runs ----------------------
+template <typename T>
+__global__ void batch_table_kernel(const BatchSweep* __restrict__ sweeps) {
+  const BatchSweep& b = sweeps[blockIdx.y];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= b.count) return;
+  PencilEntry<T>* tab = reinterpret_cast<PencilEntry<T>*>(b.table);
+  tab[idx] = b.order == 7 ? pencil_entry<T, 7>(b.a, idx) : pencil_entry<T, 5>(b.a, idx);
+}
+
+// Persistent over work items; every item is one tile of one run's sweep,
+// with its own shape, plan (256 threads) and order.
+template <typename T>
+__global__ void __launch_bounds__(256) batch_sweep_kernel(const BatchSweep* __restrict__ sweeps,
+                                                          const BatchItem* __restrict__ items,
+                                                          int nitems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchItem item = items[it];
+    const BatchSweep& b = sweeps[item.sweep];
+    const SweepArgs a = b.a;
+    const SweepPlan pl = b.p;
+    const PencilEntry<T>* tab = reinterpret_cast<const PencilEntry<T>*>(b.table);
+    if (b.order == 7)
+      sweep_tile<T, 7, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, item.tile, smem);
+    else
+      sweep_tile<T, 5, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, item.tile, smem);
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_batch_tables(int dtype, const BatchSweep* sweeps, int nsweeps, int max_count,
+                               hipStream_t s) {
+  if (nsweeps <= 0 || max_count <= 0) return hipSuccess;
+  const dim3 grid((max_count + 127) / 128, nsweeps);
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL(batch_table_kernel<double>, grid, dim3(128), 0, s, sweeps);
+  else
+    hipLaunchKernelGGL(batch_table_kernel<float>, grid, dim3(128), 0, s, sweeps);
+  return hipGetLastError();
+}
+
+hipError_t prepare_batch_sweep(int dtype, size_t lds_bytes) {
+  const void* k = dtype == SLMPP_F64 ? reinterpret_cast<const void*>(batch_sweep_kernel<double>)
+                                     : reinterpret_cast<const void*>(batch_sweep_kernel<float>);
+  if (lds_bytes > 64 * 1024)
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  return hipSuccess;
+}
+
+int batch_sweep_blocks_per_cu(int dtype, size_t lds_bytes) {
+  int per_cu = 0;
+  const void* k = dtype == SLMPP_F64 ? reinterpret_cast<const void*>(batch_sweep_kernel<double>)
+                                     : reinterpret_cast<const void*>(batch_sweep_kernel<float>);
+  if (lds_bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds_bytes) != hipSuccess)
+    return 1;
+  return per_cu > 0 ? per_cu : 1;
+}
+
+hipError_t launch_batch_sweeps(int dtype, const BatchSweep* sweeps, const BatchItem* items,
+                               int nitems, size_t lds_bytes, int grid, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL(batch_sweep_kernel<double>, dim3(grid), dim3(256), lds_bytes, s, sweeps,
+                       items, nitems);
+  else
+    hipLaunchKernelGGL(batch_sweep_kernel<float>, dim3(grid), dim3(256), lds_bytes, s, sweeps,
+                       items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_generic_sweep(int dtype, int order, const SweepArgs& a, const SweepPlan& p,
+                                const void* table, hipStream_t s) {
+  SweepPlan g = p;
+  g.R = 0;
+  g.fast = 0;
+  if (dtype == SLMPP_F64)
+    return order == 7 ? launch_k<double, 7, SLMPP_LIM_MPP, 0, 0>(a, g, table, s)
+                      : launch_k<double, 5, SLMPP_LIM_MPP, 0, 0>(a, g, table, s);
+  return order == 7 ? launch_k<float, 7, SLMPP_LIM_MPP, 0, 0>(a, g, table, s)
+                    : launch_k<float, 5, SLMPP_LIM_MPP, 0, 0>(a, g, table, s);
+}
+
+namespace {
+size_t entry_bytes_any(int dtype) { return entry_bytes(dtype); }
+}  // namespace
+
+// Plan of a batch sweep: 256 threads, W pencils per tile (W * S = 256),
+// runtime segment length.  Returns lds_bytes == 0 when W does not fit LDS.
+SweepPlan plan_batch_sweep(int dtype, int order, int32_t n, int64_t npen, int64_t inner,
+                           int32_t nfast, int W) {
+  SweepPlan p{};
+  const size_t es = dtype == SLMPP_F64 ? 8 : 4;
+  const int gh = order == 7 ? 4 : 3;
+  p.G = gh + nfast;
+  const bool contiguous = inner == 1;
+  int P = n + 2 * p.G;
+  if ((P & 1) == 0) ++P;
+  p.pitch = contiguous ? P : W;
+  const size_t elems = contiguous ? (size_t)W * P : (size_t)(n + 2 * p.G) * W;
+  size_t b = (elems * es + 15) & ~(size_t)15;
+  b += (size_t)W * entry_bytes_any(dtype) + elems * es;
+  p.W = W;
+  p.S = 256 / W;
+  p.R = 0;
+  p.threads = 256;
+  p.lds_bytes = b <= 96 * 1024 ? b : 0;
+  p.tiles = (npen + W - 1) / W;
+  p.fast = 0;
+  return p;
+}
+
 
 size_t pencil_table_bytes(int dtype, int64_t count) { return entry_bytes(dtype) * (size_t)count; }
 

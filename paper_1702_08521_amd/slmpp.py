@@ -103,6 +103,18 @@ SIGNATURES = {
     "slmpp_timing_enable": (_S, [_VP, _I32]),
     "slmpp_timing_read": (_S, [_VP, ctypes.POINTER(Timing)]),
     "slmpp_copy_device": (_S, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "slmpp_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GridDesc), _I32]),
+    "slmpp_batch_create": (_S, [ctypes.POINTER(GridDesc), ctypes.POINTER(_D), _I32,
+                                ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
+                                ctypes.POINTER(_VP)]),
+    "slmpp_batch_destroy": (_S, [_VP]),
+    "slmpp_batch_last_error": (ctypes.c_char_p, [_VP]),
+    "slmpp_batch_init_separable": (_S, [_VP, _I32, _VP, _VP, _VP, _VP]),
+    "slmpp_batch_step": (_S, [_VP, _I32]),
+    "slmpp_batch_step_eager": (_S, [_VP, _I32]),
+    "slmpp_batch_get_f": (_S, [_VP, _I32, _VP, _I64]),
+    "slmpp_batch_autotune": (_S, [_VP, ctypes.c_char_p]),
+    "slmpp_batch_tile_width": (_I32, [_VP, _I32, _I32]),
 }
 
 _lib = None
@@ -299,3 +311,97 @@ def copy_device(dst_ptr, src_ptr, nbytes, stream=None):
     st = lib().slmpp_copy_device(_VP(dst_ptr), _VP(src_ptr), int(nbytes),
                                  _VP(stream.cuda_stream) if stream is not None else None)
     _check(st, None)
+
+
+def _desc_array(descs):
+    arr = (GridDesc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = d
+    return arr
+
+
+def batch_workspace_bytes(descs) -> int:
+    return int(lib().slmpp_batch_workspace_bytes(_desc_array(descs), len(descs)))
+
+
+class Batch:
+    """An ensemble of independent runs advanced together (slmpp_batch_*).
+
+    descs: GridDesc per run (one storage type); dts: time step per run.
+    f: per-run CUDA tensors (allocated here if not given).  The workspace
+    is one uint8 CUDA tensor; all work goes to `stream`.
+    """
+
+    def __init__(self, descs, dts, fs=None, stream=None, device=None):
+        import torch
+
+        self.torch = torch
+        self.descs = list(descs)
+        n = len(self.descs)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.shapes = []
+        for d in self.descs:
+            D = d.D
+            self.shapes.append(tuple(d.nx[:D]) + tuple(d.nv[:D]))
+        tdt = torch.float64 if self.descs[0].storage == F64 else torch.float32
+        if fs is None:
+            fs = [torch.empty(sh, dtype=tdt, device=self.device) for sh in self.shapes]
+        self.f = list(fs)
+        arr = _desc_array(self.descs)
+        nbytes = int(lib().slmpp_batch_workspace_bytes(arr, n))
+        if nbytes == 0:
+            for d in self.descs:
+                st, msg = validate(d)
+                if st != OK:
+                    raise SlmppError(st, msg)
+            raise SlmppError(ERR_INVALID, "the runs cannot form a batch")
+        self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        wp = (self.work.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        dts_c = (_D * n)(*[float(x) for x in dts])
+        fp = (_VP * n)(*[t.data_ptr() for t in self.f])
+        h = _VP()
+        st = lib().slmpp_batch_create(arr, dts_c, n, fp, _VP(wp), nbytes,
+                                      _VP(self.stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise SlmppError(st, (lib().slmpp_batch_last_error(None) or b"").decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().slmpp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, st):
+        if st != OK:
+            raise SlmppError(st, (lib().slmpp_batch_last_error(self.h) or b"").decode())
+
+    def init_separable(self, run, s, gv):
+        s, ps = _host_f64(s)
+        gs = [_host_f64(g) for g in gv]
+        ptrs = [g[1] for g in gs] + [None] * (3 - len(gs))
+        self._c(lib().slmpp_batch_init_separable(self.h, int(run), ps, *ptrs))
+
+    def step(self, nsteps=1):
+        self._c(lib().slmpp_batch_step(self.h, int(nsteps)))
+
+    def step_eager(self, nsteps=1):
+        self._c(lib().slmpp_batch_step_eager(self.h, int(nsteps)))
+
+    def get_f(self, run):
+        shape = self.shapes[run] if 0 <= run < len(self.shapes) else (0,)
+        out = np.empty(shape, dtype=np.float64)
+        self._c(lib().slmpp_batch_get_f(self.h, int(run), out.ctypes.data_as(_VP), out.size))
+        return out
+
+    def autotune(self, cache_path=None):
+        self._c(lib().slmpp_batch_autotune(self.h, cache_path.encode() if cache_path else None))
+
+    def tile_width(self, run, axis):
+        return int(lib().slmpp_batch_tile_width(self.h, int(run), int(axis)))

@@ -24,6 +24,9 @@ Workloads (named by what they are):
                   mean density from k/k_J (0.5 or 1.1), SL-MPP5.
   landau_3d3v     electrostatic Landau damping in three dimensions,
                   48^3 x 48^3, x in [0, 4 pi)^3, v in [-6, 6]^3, SL-MPP7.
+  ensemble        256 independent Landau-type runs of uneven sizes (224
+                  1D1V up to 256 x 512, 32 2D2V at 32^2 x 64^2), mixed
+                  SL-MPP5/7, seeded k and amplitude.
 """
 from __future__ import annotations
 
@@ -113,6 +116,42 @@ def landau_3d3v(n=48, order=7, cfl=0.2, D=3, nv=None, amp=0.01):
              amp=amp, k=0.5, name="landau_%dd%dv" % (D, D))
     s["dt"] = cfl * spacing(0.0, L, n) / 6.0
     return s
+
+
+def landau_run(D, nx, nv, k, amp, order, cfl=0.5):
+    """Landau-type run (1 + A sum_l cos k x_l) Maxwellian on [0, 2 pi/k)^D
+    x [-6, 6]^D with dt at x-CFL `cfl` for the fastest velocity."""
+    L = 2.0 * math.pi / k
+    s = spec(D, nx, nv, 0.0, L, -6.0, 6.0, order=order, kappa=-1.0, ic="landau_sum",
+             amp=amp, k=k, name="landau_%dd%dv" % (D, D))
+    s["dt"] = cfl * spacing(0.0, L, nx) / 6.0
+    return s
+
+
+ENSEMBLE_SEED = 170208521
+
+
+def ensemble(n_runs=256, n_2d=32, seed=ENSEMBLE_SEED, nx_1d=(32, 48, 64, 96, 128, 192, 256),
+             nv_1d=(64, 96, 128, 192, 256, 384, 512), shape_2d=(32, 64)):
+    """Seeded ensemble of independent Landau-type runs of uneven sizes:
+    n_runs - n_2d 1D1V runs with N_x, N_v drawn from the lists, n_2d 2D2V
+    runs at shape_2d[0]^2 x shape_2d[1]^2; k ~ U[0.3, 0.6], amplitude
+    ~ logU[1e-3, 0.5], order 5 or 7 with equal odds, dt at x-CFL 0.5."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for r in range(n_runs):
+        two = r >= n_runs - n_2d
+        k = float(rng.uniform(0.3, 0.6))
+        amp = float(math.exp(rng.uniform(math.log(1e-3), math.log(0.5))))
+        order = 5 if rng.random() < 0.5 else 7
+        if two:
+            nx, nv, D = shape_2d[0], shape_2d[1], 2
+        else:
+            nx = int(rng.choice(nx_1d))
+            nv = int(rng.choice(nv_1d))
+            D = 1
+        runs.append(landau_run(D, nx, nv, k, amp, order))
+    return runs
 
 
 def advection_1d1v(nx, nv, v_lo, v_hi, profile, order=5, limiter=LIM_MPP):

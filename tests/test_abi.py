@@ -99,3 +99,80 @@ def test_copy_rejects_misaligned():
     L = slmpp.lib()
     assert L.slmpp_copy_device(ctypes.c_void_p(16), ctypes.c_void_p(32), 17, None) == slmpp.ERR_INVALID
     assert L.slmpp_copy_device(None, ctypes.c_void_p(32), 16, None) == slmpp.ERR_INVALID
+
+
+# ---- batched ensembles: host-side validation (no device work) ----------
+def _ensemble():
+    return [slmpp.make_desc(workloads.landau_1d1v(nx=16, nv=32), slmpp.F32),
+            slmpp.make_desc(workloads.twostream_1d1v(nx=32, nv=48, order=7), slmpp.F32),
+            slmpp.make_desc(workloads.landau_3d3v(n=4, nv=6, order=5, D=2), slmpp.F32)]
+
+
+def test_batch_workspace_bytes_valid_and_invalid():
+    descs = _ensemble()
+    total = slmpp.batch_workspace_bytes(descs)
+    assert total > 0
+    # grows with the ensemble
+    assert slmpp.batch_workspace_bytes(descs + descs) > total
+    # mixed storage types cannot form a batch
+    mixed = _ensemble()
+    mixed[1].storage = slmpp.F64
+    assert slmpp.batch_workspace_bytes(mixed) == 0
+    # batched runs use the SL-MPP limiter
+    lim = _ensemble()
+    lim[0].limiter = slmpp.LIM_MP
+    assert slmpp.batch_workspace_bytes(lim) == 0
+    # at most 2048 spatial cells per run
+    big = _ensemble()
+    big[0].nx[0] = 4096
+    assert slmpp.batch_workspace_bytes(big) == 0
+    # an invalid description anywhere
+    bad = _ensemble()
+    bad[2].order = 6
+    assert slmpp.batch_workspace_bytes(bad) == 0
+    assert slmpp.lib().slmpp_batch_workspace_bytes(None, 3) == 0
+
+
+def test_batch_create_rejects_before_device_work():
+    L = slmpp.lib()
+    descs = _ensemble()
+    arr = slmpp._desc_array(descs)
+    n = len(descs)
+    dts = (ctypes.c_double * n)(0.1, 0.1, float("nan"))
+    fp = (ctypes.c_void_p * n)(256, 512, 768)
+    out = ctypes.c_void_p()
+    need = slmpp.batch_workspace_bytes(descs)
+    # NULL out
+    assert L.slmpp_batch_create(arr, dts, n, fp, ctypes.c_void_p(4096), need, None, None) == slmpp.ERR_INVALID
+    # non-finite dt
+    st = L.slmpp_batch_create(arr, dts, n, fp, ctypes.c_void_p(4096), need, None, ctypes.byref(out))
+    assert st == slmpp.ERR_NONFINITE and not out.value
+    assert b"dt" in L.slmpp_batch_last_error(None)
+    dts[2] = 0.1
+    # misaligned workspace
+    st = L.slmpp_batch_create(arr, dts, n, fp, ctypes.c_void_p(4100), need, None, ctypes.byref(out))
+    assert st == slmpp.ERR_INVALID
+    # too small a workspace
+    st = L.slmpp_batch_create(arr, dts, n, fp, ctypes.c_void_p(4096), need - 1, None, ctypes.byref(out))
+    assert st == slmpp.ERR_WORKSPACE
+    # misaligned f
+    fp[1] = 520
+    st = L.slmpp_batch_create(arr, dts, n, fp, ctypes.c_void_p(4096), need, None, ctypes.byref(out))
+    assert st == slmpp.ERR_INVALID
+    # invalid description: the message names the run
+    bad = _ensemble()
+    bad[1].D = 4
+    st = L.slmpp_batch_create(slmpp._desc_array(bad), dts, n, fp, ctypes.c_void_p(4096), need, None,
+                              ctypes.byref(out))
+    assert st == slmpp.ERR_INVALID and b"run 1" in L.slmpp_batch_last_error(None)
+
+
+def test_batch_null_handle_calls():
+    L = slmpp.lib()
+    assert L.slmpp_batch_destroy(None) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_step(None, 1) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_step_eager(None, 1) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_get_f(None, 0, None, 0) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_autotune(None, None) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_init_separable(None, 0, None, None, None, None) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_tile_width(None, 0, 0) == 0
