@@ -264,7 +264,7 @@ slmpp_status slmpp_batch_step_eager(slmpp_batch* b, int32_t nsteps);
 slmpp_status slmpp_batch_get_f(slmpp_batch* b, int32_t run, double* f_host, int64_t n);
 
 /* Choose the tile width of every distinct pencil shape of the ensemble by
- * timing the candidates (64, 32, 16, 8 pencils per 256-thread tile) on a
+ * timing the candidates (128, 64, 32, 16, 8 pencils per 256-thread tile) on a
  * scratch copy of a run's data.  cache_path (may be NULL) is a text file
  * of "dtype order n inner W" lines: shapes found there are not re-timed,
  * and new choices are appended.  Synchronises. */

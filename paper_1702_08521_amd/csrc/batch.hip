@@ -23,33 +23,38 @@ __device__ __forceinline__ void kadd(KSum& a, double x) {
   a.s = t;
 }
 
-// items[i] = (run, spatial cell); one workgroup per item, fixed order.
+// items[i] = (run, spatial cell); one wavefront per item.  Each lane sums
+// its strided share of the velocity row (compensated), then the lanes are
+// combined by a fixed shuffle tree, so the result does not depend on timing.
 template <typename T>
 __global__ void __launch_bounds__(256) batch_moment_kernel(const BatchRun* __restrict__ runs,
                                                            const int2* __restrict__ items,
                                                            int nitems) {
-  __shared__ double ss[256], sc[256];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int it = blockIdx.x * 4 + wave; it < nitems; it += gridDim.x * 4) {
     const int2 item = items[it];
     const BatchRun& r = runs[item.x];
     const T* b = reinterpret_cast<const T*>(r.f) + (int64_t)item.y * r.nvs;
     KSum acc{0.0, 0.0};
-    for (int64_t k = threadIdx.x; k < r.nvs; k += 256) kadd(acc, (double)b[k]);
-    ss[threadIdx.x] = acc.s;
-    sc[threadIdx.x] = acc.c;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        KSum a{ss[threadIdx.x], sc[threadIdx.x]};
-        kadd(a, ss[threadIdx.x + off]);
-        a.c += sc[threadIdx.x + off];
-        ss[threadIdx.x] = a.s;
-        sc[threadIdx.x] = a.c;
-      }
-      __syncthreads();
+    constexpr int U = 4;
+    int64_t k = lane;
+    for (; k + (U - 1) * 64 < r.nvs; k += U * 64) {
+      T x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = b[k + u * 64];
+#pragma unroll
+      for (int u = 0; u < U; ++u) kadd(acc, (double)x[u]);
     }
-    if (threadIdx.x == 0) r.rho[item.y] = r.dvol * (ss[0] + sc[0]);
-    __syncthreads();
+    for (; k < r.nvs; k += 64) kadd(acc, (double)b[k]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double os = __shfl_down(acc.s, off, 64);
+      const double oc = __shfl_down(acc.c, off, 64);
+      kadd(acc, os);
+      acc.c += oc;
+    }
+    if (lane == 0) r.rho[item.y] = r.dvol * (acc.s + acc.c);
   }
 }
 
@@ -62,24 +67,22 @@ __device__ __forceinline__ double lap_symbol(double th, int order) {
 }
 
 // In-LDS DFT of a D-dimensional complex array along axis l:
-// out[.., k, ..] = sum_m in[.., m, ..] exp(sign 2 pi i m k / n)
-__device__ void lds_dft(const double2* in, double2* out, int D, const int64_t* nx, int l,
+// out[.., k, ..] = sum_m in[.., m, ..] exp(sign 2 pi i m k / n), with the
+// n roots of unity of the axis in tw (cos, sin of 2 pi q / n).  Sizes are
+// at most kBatchMaxSpace, so 32-bit index arithmetic.
+__device__ void lds_dft(const double2* in, double2* out, const double2* tw, int inner, int n,
                         int sign, int total) {
-  int64_t inner = 1;
-  for (int k = l + 1; k < D; ++k) inner *= nx[k];
-  const int n = (int)nx[l];
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int j = (int)(t % inner);
-    const int k = (int)((t / inner) % n);
-    const int o = (int)(t / (inner * n));
-    const double2* src = in + (int64_t)o * n * inner + j;
+    const int j = t % inner;
+    const int k = (t / inner) % n;
+    const int o = t / (inner * n);
+    const double2* src = in + o * n * inner + j;
     double sr = 0.0, si = 0.0;
     int q = 0;
     for (int m = 0; m < n; ++m) {
-      double sn, cs;
-      sincospi(2.0 * (double)q / (double)n, &sn, &cs);
-      sn *= sign;
-      const double2 x = src[(int64_t)m * inner];
+      const double cs = tw[q].x;
+      const double sn = sign * tw[q].y;
+      const double2 x = src[m * inner];
       sr += x.x * cs - x.y * sn;
       si += x.x * sn + x.y * cs;
       q += k;
@@ -90,41 +93,59 @@ __device__ void lds_dft(const double2* in, double2* out, int D, const int64_t* n
 }
 
 // One workgroup per run: rho -> phi_hat = G rho_hat -> phi -> accel.
+// LDS: two complex work arrays, then per axis the roots of unity and the
+// Laplacian symbol sym_l(k) / h_l^2 (see poisson_lds).
 __global__ void __launch_bounds__(256) batch_poisson_kernel(const BatchRun* __restrict__ runs) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BatchRun& r = runs[blockIdx.x];
   const int D = r.D;
   const int total = (int)r.nxs;
+  int nx[3] = {1, 1, 1}, inner[3] = {1, 1, 1}, toff[3] = {0, 0, 0};
+  int ntw = 0;
+  for (int l = 0; l < D; ++l) {
+    nx[l] = (int)r.nx[l];
+    toff[l] = ntw;
+    ntw += nx[l];
+  }
+  for (int l = D - 2; l >= 0; --l) inner[l] = inner[l + 1] * nx[l + 1];
   double2* A = reinterpret_cast<double2*>(smem);
   double2* B = A + total;
+  double2* tw = B + total;  // roots of unity of axis l at tw + toff[l]
+  double* sym = reinterpret_cast<double*>(tw + ntw);  // symbol of axis l at sym + toff[l]
+  for (int t = threadIdx.x; t < ntw; t += blockDim.x) {
+    int l = 0;
+    while (l + 1 < D && t >= toff[l + 1]) ++l;
+    const int k = t - toff[l];
+    double sn, cs;
+    sincospi(2.0 * (double)k / (double)nx[l], &sn, &cs);
+    tw[t] = make_double2(cs, sn);
+    sym[t] = lap_symbol(2.0 * M_PI * (double)k / (double)nx[l], r.poisson_order) / (r.h[l] * r.h[l]);
+  }
   for (int t = threadIdx.x; t < total; t += blockDim.x) A[t] = make_double2(r.rho[t], 0.0);
   __syncthreads();
   double2* cur = A;
   double2* oth = B;
   for (int l = 0; l < D; ++l) {
-    lds_dft(cur, oth, D, r.nx, l, -1, total);
+    lds_dft(cur, oth, tw + toff[l], inner[l], nx[l], -1, total);
     __syncthreads();
     double2* tmp = cur;
     cur = oth;
     oth = tmp;
   }
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    int64_t rem = t;
     double L = 0.0;
     bool zero = true;
-    for (int l = D - 1; l >= 0; --l) {
-      const int64_t k = rem % r.nx[l];
-      rem /= r.nx[l];
+    for (int l = 0; l < D; ++l) {
+      const int k = (t / inner[l]) % nx[l];
       if (k) zero = false;
-      const double th = 2.0 * M_PI * (double)k / (double)r.nx[l];
-      L += lap_symbol(th, r.poisson_order) / (r.h[l] * r.h[l]);
+      L += sym[toff[l] + k];
     }
     const double g = zero ? 0.0 : r.kappa / L;
     cur[t] = make_double2(cur[t].x * g, cur[t].y * g);
   }
   __syncthreads();
   for (int l = 0; l < D; ++l) {
-    lds_dft(cur, oth, D, r.nx, l, +1, total);
+    lds_dft(cur, oth, tw + toff[l], inner[l], nx[l], +1, total);
     __syncthreads();
     double2* tmp = cur;
     cur = oth;
@@ -139,17 +160,15 @@ __global__ void __launch_bounds__(256) batch_poisson_kernel(const BatchRun* __re
   }
   __syncthreads();
   for (int l = 0; l < D; ++l) {
-    int64_t inner = 1;
-    for (int k = l + 1; k < D; ++k) inner *= r.nx[k];
-    const int64_t n = r.nx[l];
+    const int n = nx[l], in = inner[l];
     const double h = r.h[l];
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
-      const int64_t i = (t / inner) % n;
-      const double* base = phi + (t - i * inner);
-      auto P = [&](int64_t k) {
-        int64_t q = (i + k) % n;
+      const int i = (t / in) % n;
+      const double* base = phi + (t - i * in);
+      auto P = [&](int k) {
+        int q = (i + k) % n;
         if (q < 0) q += n;
-        return base[q * inner];
+        return base[q * in];
       };
       double d;
       if (r.poisson_order == 2)
@@ -168,7 +187,8 @@ __global__ void __launch_bounds__(256) batch_poisson_kernel(const BatchRun* __re
 hipError_t launch_batch_moment(int dtype, const BatchRun* runs, const int2* items, int nitems,
                                hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  const int grid = nitems < 65536 ? nitems : 65536;
+  const int blocks = (nitems + 3) / 4;
+  const int grid = blocks < 65536 ? blocks : 65536;
   if (dtype == SLMPP_F64)
     hipLaunchKernelGGL(batch_moment_kernel<double>, dim3(grid), dim3(256), 0, s, runs, items, nitems);
   else
@@ -178,9 +198,17 @@ hipError_t launch_batch_moment(int dtype, const BatchRun* runs, const int2* item
 
 hipError_t prepare_batch_sweep(int dtype, size_t lds_bytes);
 
+namespace {
+// two complex work arrays, plus a root of unity and a symbol value for
+// every index of every axis (sum_l nx_l <= prod(nx) + 2 entries)
+size_t poisson_lds(int max_nxs) {
+  return sizeof(double2) * 2 * (size_t)max_nxs + (sizeof(double2) + sizeof(double)) * ((size_t)max_nxs + 2);
+}
+}  // namespace
+
 hipError_t prepare_batch_kernels(int dtype, size_t sweep_lds, int max_nxs) {
   hipError_t e = prepare_batch_sweep(dtype, sweep_lds);
-  const size_t lds = 2 * sizeof(double2) * (size_t)max_nxs;
+  const size_t lds = poisson_lds(max_nxs);
   if (e == hipSuccess && lds > 64 * 1024)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(batch_poisson_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -189,7 +217,7 @@ hipError_t prepare_batch_kernels(int dtype, size_t sweep_lds, int max_nxs) {
 
 hipError_t launch_batch_poisson(const BatchRun* runs, int nruns, int max_nxs, hipStream_t s) {
   if (nruns <= 0) return hipSuccess;
-  const size_t lds = 2 * sizeof(double2) * (size_t)max_nxs;
+  const size_t lds = poisson_lds(max_nxs);
   hipLaunchKernelGGL(batch_poisson_kernel, dim3(nruns), dim3(256), lds, s, runs);
   return hipGetLastError();
 }

@@ -64,7 +64,7 @@ std::vector<SlotDef> slot_defs(int Dmax, int& npre) {
   return s;
 }
 
-const int kCandidates[] = {64, 32, 16, 8};
+const int kCandidates[] = {128, 64, 32, 16, 8};
 constexpr int kMinW = 8;
 
 struct Layout {
@@ -240,12 +240,24 @@ struct slmpp_batch {
     return true;
   }
 
+  // Without timings: the widest tile within the LDS budget, register
+  // variants first; else the tile of least LDS.
   int default_width(int order, const SweepArgs& a) const {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int W : kCandidates) {
+        SweepPlan p = plan_batch_sweep(dtype, order, a.n, a.npen, a.inner, a.nfast, W);
+        if (p.lds_bytes && p.lds_bytes <= kBatchTileLds && (pass == 1 || p.R > 0)) return W;
+      }
+    int bestW = 0;
+    size_t least = 0;
     for (int W : kCandidates) {
       SweepPlan p = plan_batch_sweep(dtype, order, a.n, a.npen, a.inner, a.nfast, W);
-      if (p.lds_bytes) return W;
+      if (p.lds_bytes && (!bestW || p.lds_bytes < least)) {
+        bestW = W;
+        least = p.lds_bytes;
+      }
     }
-    return 0;
+    return bestW;
   }
 
   // Build the grouped launch lists from the current tile widths and upload.
@@ -262,9 +274,15 @@ struct slmpp_batch {
         int64_t count = 0;
         if (!sweep_of(r, slots[si], a, count)) continue;
         const std::string key = shape_key(dtype, d[r].order, a.n, a.inner);
-        int W = width.count(key) ? width[key] : default_width(d[r].order, a);
-        SweepPlan p = W ? plan_batch_sweep(dtype, d[r].order, a.n, a.npen, a.inner, a.nfast, W)
-                        : SweepPlan{};
+        // a width from the autotuner or its cache, else (or when it does
+        // not fit this shape) the default
+        int W = width.count(key) ? width[key] : 0;
+        SweepPlan p{};
+        if (W) p = plan_batch_sweep(dtype, d[r].order, a.n, a.npen, a.inner, a.nfast, W);
+        if (!p.lds_bytes) {
+          W = default_width(d[r].order, a);
+          if (W) p = plan_batch_sweep(dtype, d[r].order, a.n, a.npen, a.inner, a.nfast, W);
+        }
         if (!p.lds_bytes)
           return fail(SLMPP_ERR_SHAPE, "run " + std::to_string(r) + ": pencils of " +
                                            std::to_string(a.n) + " cells do not fit a batch tile");
@@ -571,9 +589,8 @@ slmpp_status slmpp_batch_get_f(slmpp_batch* b, int32_t run, double* f_host, int6
 slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path) {
   if (!b) return SLMPP_ERR_INVALID;
   // candidates are timed with the runs' real speeds
-  slmpp_status fst = b->ensure_field();
-  if (fst != SLMPP_OK) return fst;
-  // known choices
+  slmpp_status st = b->ensure_field();
+  if (st != SLMPP_OK) return st;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -582,64 +599,135 @@ slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path) {
       std::string dt;
       int order = 0, W = 0;
       int64_t n = 0, inner = 0;
-      if (is >> dt >> order >> n >> inner >> W) {
+      if (is >> dt >> order >> n >> inner >> W &&
+          (W == 128 || W == 64 || W == 32 || W == 16 || W == 8)) {
         const int dtype = dt == "f64" ? SLMPP_F64 : SLMPP_F32;
         b->width[shape_key(dtype, order, n, inner)] = W;
       }
     }
   }
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return b->fail(SLMPP_ERR_DEVICE, "event create");
-  std::vector<std::string> fresh;
-  const size_t es = b->dtype == SLMPP_F64 ? 8 : 4;
-  slmpp_status result = SLMPP_OK;
-  for (size_t si = 0; si < b->slots.size() && result == SLMPP_OK; ++si) {
-    for (int r = 0; r < b->nruns && result == SLMPP_OK; ++r) {
+  // one representative sweep per pencil shape not known yet
+  struct Rep {
+    std::string key;
+    int r;
+    SweepArgs a;
+    int64_t count;
+  };
+  std::vector<Rep> reps;
+  for (size_t si = 0; si < b->slots.size(); ++si)
+    for (int r = 0; r < b->nruns; ++r) {
       SweepArgs a;
       int64_t count = 0;
       if (!b->sweep_of(r, b->slots[si], a, count)) continue;
       const std::string key = shape_key(b->dtype, b->d[r].order, a.n, a.inner);
-      if (b->width.count(key)) continue;
-      // time the candidates on a scratch copy of run r
-      void* scratch = b->work + b->lay.scratch;
-      hipError_t e = hipMemcpyAsync(scratch, b->f[r], es * b->g[r].ncell, hipMemcpyDeviceToDevice,
-                                    b->stream);
-      a.f = scratch;
-      if (e == hipSuccess) e = launch_pencil_table(b->dtype, b->d[r].order, a, b->work + b->lay.tab[r],
-                                                   count, b->stream);
-      int bestW = 0;
-      float best = 1e30f;
+      bool seen = b->width.count(key) > 0;
+      for (const Rep& q : reps) seen = seen || q.key == key;
+      if (!seen) reps.push_back(Rep{key, r, a, count});
+    }
+  int n_cu = 1, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return b->fail(SLMPP_ERR_DEVICE, "device query");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return b->fail(SLMPP_ERR_DEVICE, "event create");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return b->fail(SLMPP_ERR_DEVICE, "event create");
+  }
+  const size_t es = b->dtype == SLMPP_F64 ? 8 : 4;
+  const int64_t scratch_elems = (int64_t)(b->lay.stage - b->lay.scratch) / (int64_t)es;
+  char* scratch = b->work + b->lay.scratch;
+  BatchSweep* dsw = b->at<BatchSweep>(b->lay.sweeps);
+  BatchItem* dit = b->at<BatchItem>(b->lay.items);
+  std::vector<std::string> fresh;
+  std::vector<BatchSweep> hsw;
+  std::vector<BatchItem> hit;
+  hipError_t e = hipSuccess;
+  for (const Rep& q : reps) {
+    const int64_t ncell = b->g[q.r].ncell;
+    const int64_t tiles8 = (q.a.npen + kMinW - 1) / kMinW;
+    // copies of the run: enough tiles to fill the GPU, within the scratch
+    // and work-list capacities
+    int64_t m = std::max<int64_t>(1, ((int64_t)1 << 22) / ncell);
+    m = std::min(m, scratch_elems / ncell);
+    m = std::min(m, b->lay.max_sweeps);
+    m = std::min(m, b->lay.max_items / std::max<int64_t>(tiles8, 1));
+    m = std::max<int64_t>(m, 1);
+    e = hipMemcpyAsync(scratch, b->f[q.r], es * ncell, hipMemcpyDeviceToDevice, b->stream);
+    for (int64_t k = 1; k < m && e == hipSuccess; k *= 2) {
+      const int64_t c = std::min(k, m - k);
+      e = hipMemcpyAsync(scratch + es * ncell * k, scratch, es * ncell * c, hipMemcpyDeviceToDevice,
+                         b->stream);
+    }
+    if (e != hipSuccess) break;
+    // candidates within the LDS budget when there are any
+    std::vector<SweepPlan> cand;
+    for (int W : kCandidates) {
+      SweepPlan p = plan_batch_sweep(b->dtype, b->d[q.r].order, q.a.n, q.a.npen, q.a.inner,
+                                     q.a.nfast, W);
+      if (p.lds_bytes && p.lds_bytes <= kBatchTileLds) cand.push_back(p);
+    }
+    if (cand.empty())
       for (int W : kCandidates) {
-        if (e != hipSuccess) break;
-        SweepPlan p = plan_batch_sweep(b->dtype, b->d[r].order, a.n, a.npen, a.inner, a.nfast, W);
-        if (!p.lds_bytes) continue;
-        e = launch_generic_sweep(b->dtype, b->d[r].order, a, p, b->work + b->lay.tab[r], b->stream);
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
-          e = launch_generic_sweep(b->dtype, b->d[r].order, a, p, b->work + b->lay.tab[r], b->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && ms < best) {
-          best = ms;
-          bestW = W;
-        }
+        SweepPlan p = plan_batch_sweep(b->dtype, b->d[q.r].order, q.a.n, q.a.npen, q.a.inner,
+                                       q.a.nfast, W);
+        if (p.lds_bytes) cand.push_back(p);
       }
-      if (e != hipSuccess) {
-        result = b->hip_fail(e, "autotune");
-        break;
+    int bestW = 0;
+    float best = 1e30f;
+    for (const SweepPlan& p : cand) {
+      hsw.assign((size_t)m, BatchSweep{});
+      hit.clear();
+      for (int64_t k = 0; k < m; ++k) {
+        BatchSweep& w = hsw[(size_t)k];
+        w.a = q.a;
+        w.a.f = scratch + es * ncell * k;
+        w.p = p;
+        w.table = b->work + b->lay.tab[q.r];
+        w.order = b->d[q.r].order;
+        w.count = (int32_t)q.count;
+        for (int64_t t = 0; t < p.tiles; ++t) hit.push_back(BatchItem{(int32_t)k, 0, t});
       }
-      if (bestW) {
-        b->width[key] = bestW;
-        fresh.push_back(key + " " + std::to_string(bestW));
+      e = hipMemcpyAsync(dsw, hsw.data(), sizeof(BatchSweep) * hsw.size(), hipMemcpyHostToDevice,
+                         b->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dit, hit.data(), sizeof(BatchItem) * hit.size(), hipMemcpyHostToDevice,
+                           b->stream);
+      if (e == hipSuccess) e = prepare_batch_kernels(b->dtype, p.lds_bytes, b->max_nxs);
+      if (e == hipSuccess) e = launch_batch_tables(b->dtype, dsw, 1, (int)q.count, b->stream);
+      const int nit = (int)hit.size();
+      const int grid =
+          std::max(1, std::min(nit, batch_sweep_blocks_per_cu(b->dtype, p.lds_bytes) * n_cu));
+      if (e == hipSuccess) e = launch_batch_sweeps(b->dtype, dsw, dit, nit, p.lds_bytes, grid, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+        e = launch_batch_sweeps(b->dtype, dsw, dit, nit, p.lds_bytes, grid, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      if (ms < best) {
+        best = ms;
+        bestW = p.W;
       }
+    }
+    if (e != hipSuccess) break;
+    if (bestW) {
+      b->width[q.key] = bestW;
+      fresh.push_back(q.key + " " + std::to_string(bestW));
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (result != SLMPP_OK) return result;
+  if (e != hipSuccess) {
+    b->hip_fail(e, "autotune");
+    // the work lists were overwritten: restore them before reporting
+    const std::string msg = b->err;
+    b->build();
+    b->err = msg;
+    return SLMPP_ERR_DEVICE;
+  }
   if (cache_path && !fresh.empty()) {
     std::ofstream out(cache_path, std::ios::app);
     for (const auto& l : fresh) out << l << '\n';

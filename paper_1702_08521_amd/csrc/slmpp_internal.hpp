@@ -108,6 +108,10 @@ hipError_t launch_batch_poisson(const BatchRun* runs, int nruns, int max_nxs, hi
 // Kernel attributes for the LDS sizes of a batch (outside any graph capture).
 hipError_t prepare_batch_kernels(int dtype, size_t sweep_lds, int max_nxs);
 constexpr int kBatchMaxSpace = 2048;  // spatial cells per run (one-workgroup Poisson)
+// LDS of one batch tile: preferred budget (at least five 256-thread
+// workgroups per CU) and hard limit
+constexpr size_t kBatchTileLds = 32 * 1024;
+constexpr size_t kBatchTileLdsMax = 96 * 1024;
 
 // ---- field kernels (field.hip) ----
 hipError_t launch_moment(int dtype, const void* f, int64_t nxs, int64_t nvs, double dvol,

@@ -905,7 +905,9 @@ __global__ void batch_table_kernel(const BatchSweep* __restrict__ sweeps) {
 }
 
 // Persistent over work items; every item is one tile of one run's sweep,
-// with its own shape, plan (256 threads) and order.
+// with its own shape, plan (256 threads) and order.  Segments of 8, 12 or
+// 16 cells per thread (pl.R) take the compile-time variants, which keep a
+// segment's outputs in registers; other lengths take the runtime one.
 template <typename T>
 __global__ void __launch_bounds__(256) batch_sweep_kernel(const BatchSweep* __restrict__ sweeps,
                                                           const BatchItem* __restrict__ items,
@@ -917,10 +919,17 @@ __global__ void __launch_bounds__(256) batch_sweep_kernel(const BatchSweep* __re
     const SweepArgs a = b.a;
     const SweepPlan pl = b.p;
     const PencilEntry<T>* tab = reinterpret_cast<const PencilEntry<T>*>(b.table);
-    if (b.order == 7)
-      sweep_tile<T, 7, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, item.tile, smem);
-    else
-      sweep_tile<T, 5, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, item.tile, smem);
+    const int64_t t = item.tile;
+    switch (b.order * 100 + pl.R) {
+      case 508: sweep_tile<T, 5, SLMPP_LIM_MPP, 8, 0>(a, pl, tab, t, smem); break;
+      case 512: sweep_tile<T, 5, SLMPP_LIM_MPP, 12, 0>(a, pl, tab, t, smem); break;
+      case 516: sweep_tile<T, 5, SLMPP_LIM_MPP, 16, 0>(a, pl, tab, t, smem); break;
+      case 708: sweep_tile<T, 7, SLMPP_LIM_MPP, 8, 0>(a, pl, tab, t, smem); break;
+      case 712: sweep_tile<T, 7, SLMPP_LIM_MPP, 12, 0>(a, pl, tab, t, smem); break;
+      case 716: sweep_tile<T, 7, SLMPP_LIM_MPP, 16, 0>(a, pl, tab, t, smem); break;
+      case 700: sweep_tile<T, 7, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, t, smem); break;
+      default: sweep_tile<T, 5, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, t, smem); break;
+    }
     __syncthreads();
   }
 }
@@ -985,8 +994,11 @@ namespace {
 size_t entry_bytes_any(int dtype) { return entry_bytes(dtype); }
 }  // namespace
 
-// Plan of a batch sweep: 256 threads, W pencils per tile (W * S = 256),
-// runtime segment length.  Returns lds_bytes == 0 when W does not fit LDS.
+// Plan of a batch sweep: 256 threads, W pencils per tile (W * S = 256).
+// A pencil length n = S * R with R in {8, 12, 16} takes the register
+// variant (R); others the runtime segment length (R = 0), which also keeps
+// its outputs in a second LDS tile.  lds_bytes == 0: the tile does not fit
+// kBatchTileLdsMax.
 SweepPlan plan_batch_sweep(int dtype, int order, int32_t n, int64_t npen, int64_t inner,
                            int32_t nfast, int W) {
   SweepPlan p{};
@@ -997,14 +1009,16 @@ SweepPlan plan_batch_sweep(int dtype, int order, int32_t n, int64_t npen, int64_
   int P = n + 2 * p.G;
   if ((P & 1) == 0) ++P;
   p.pitch = contiguous ? P : W;
-  const size_t elems = contiguous ? (size_t)W * P : (size_t)(n + 2 * p.G) * W;
-  size_t b = (elems * es + 15) & ~(size_t)15;
-  b += (size_t)W * entry_bytes_any(dtype) + elems * es;
   p.W = W;
   p.S = 256 / W;
-  p.R = 0;
   p.threads = 256;
-  p.lds_bytes = b <= 96 * 1024 ? b : 0;
+  const int R = n % p.S == 0 ? n / p.S : 0;
+  p.R = (R == 8 || R == 12 || R == 16) ? R : 0;
+  const size_t elems = contiguous ? (size_t)W * P : (size_t)(n + 2 * p.G) * W;
+  size_t b = (elems * es + 15) & ~(size_t)15;
+  b += (size_t)W * entry_bytes_any(dtype);
+  if (p.R == 0) b += elems * es;
+  p.lds_bytes = b <= kBatchTileLdsMax ? b : 0;
   p.tiles = (npen + W - 1) / W;
   p.fast = 0;
   return p;
