@@ -128,7 +128,8 @@ size_t slmpp_workspace_bytes(const slmpp_grid_desc* desc);
 slmpp_status slmpp_validate(const slmpp_grid_desc* desc, char* msg, size_t msg_len);
 
 /* Create a context.  f_dev: caller-owned device array of the grid's cells
- * in the storage type; it must stay allocated and unmoved until destroy.
+ * in the storage type, 16-byte aligned; it must stay allocated and unmoved
+ * until destroy.
  * work_dev/work_bytes: caller-owned device workspace of at least
  * slmpp_workspace_bytes(desc) bytes, 256-byte aligned.  hip_stream: the
  * hipStream_t all work is enqueued on (NULL = the null stream).  On

@@ -26,8 +26,8 @@ thread_local std::string g_error;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, total;
-  int64_t stage_doubles;
+  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, mom, total;
+  int64_t stage_doubles, mom_doubles;
 };
 
 int64_t n_space(const slmpp_grid_desc& d) {
@@ -69,6 +69,9 @@ Layout layout_of(const slmpp_grid_desc& d) {
   L.table = take(pencil_table_bytes(SLMPP_F64, std::max<int64_t>(maxnv, nxs)));
   L.stage_doubles = std::max<int64_t>(std::min<int64_t>(kStageChunk, ncell), nxs + sumnv);
   L.stage = take(sizeof(double) * L.stage_doubles);
+  // row sums of the x_1 sweep's 64-pencil tiles (fused velocity moment)
+  L.mom_doubles = ncell / 64;
+  L.mom = take(sizeof(double) * std::max<int64_t>(L.mom_doubles, 1));
   L.total = off;
   return L;
 }
@@ -177,6 +180,7 @@ struct slmpp_ctx {
   double* diagfield() { return reinterpret_cast<double*>(work + lay.diagfield); }
   double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
   void* table() { return work + lay.table; }
+  double* mom() { return reinterpret_cast<double*>(work + lay.mom); }
   size_t esize() const { return d.storage == SLMPP_F64 ? 8 : 4; }
 
   slmpp_status fail(slmpp_status code, const char* fmt, ...) {
@@ -232,7 +236,12 @@ struct slmpp_ctx {
   }
 
   // --- one sweep along array axis a ---
-  slmpp_status sweep(int a, double dt, const double* accel_dev) {
+  // fuse_moment (x_1 sweeps only): when the sweep runs as strided 64-pencil
+  // tiles lying within velocity blocks, it also leaves per-tile row sums for
+  // the velocity moment and *fused is set.
+  slmpp_status sweep(int a, double dt, const double* accel_dev, bool fuse_moment = false,
+                     bool* fused = nullptr) {
+    if (fused) *fused = false;
     const int nd = 2 * D;
     int64_t inner = 1;
     for (int k = a + 1; k < nd; ++k) inner *= dims[k];
@@ -274,6 +283,11 @@ struct slmpp_ctx {
     SweepPlan p = plan_sweep(d.storage, d.order, d.limiter, s.n, s.npen, inner, s.nfast);
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
+    if (fuse_moment && a == 0 && p.fast && p.W == 64 && inner > 1 && nvs % 64 == 0 &&
+        p.tiles * (int64_t)s.n <= lay.mom_doubles) {
+      s.mom = mom();
+      if (fused) *fused = true;
+    }
     const double cells = (double)ncell;
     const int64_t tcount = a < D ? d.nv[a] : nxs;
     hipError_t e = tic(5, 0.0, 0.0);
@@ -305,6 +319,21 @@ struct slmpp_ctx {
     if (e == hipSuccess) e = toc();
     if (e != hipSuccess) return hip_fail(e, "poisson launch");
     return SLMPP_OK;
+  }
+
+  // the field after an x_1 sweep that left its tile row sums (see sweep)
+  slmpp_status field_from_rowsums() {
+    double dvol = 1.0;
+    for (int l = 0; l < D; ++l) dvol *= hv[l];
+    const int n = (int)d.nx[0];
+    const int64_t ncol = nxs / n, nsub = nvs / 64;
+    hipError_t e = tic(2, 8.0 * (double)ncol * nsub * n + 8.0 * nxs, 0.0);
+    if (e == hipSuccess) e = launch_moment_reduce(mom(), n, ncol, nsub, dvol, rho(), stream);
+    if (e == hipSuccess) e = toc();
+    if (e != hipSuccess) return hip_fail(e, "moment reduce launch");
+    slmpp_status st = poisson(rho(), phi(), accel());
+    if (st == SLMPP_OK) field_valid = true;
+    return st;
   }
 
   slmpp_status field() {
@@ -571,8 +600,9 @@ slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
     if (!c->field_valid) st = c->field();
     for (int l = 0; l < D && st == SLMPP_OK; ++l)
       st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
-    for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l) st = c->sweep(l, dt, nullptr);
-    if (st == SLMPP_OK) st = c->field();
+    bool fused = false;
+    for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l) st = c->sweep(l, dt, nullptr, l == 0, &fused);
+    if (st == SLMPP_OK) st = fused ? c->field_from_rowsums() : c->field();
     for (int l = 0; l < D && st == SLMPP_OK; ++l)
       st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
     if (st != SLMPP_OK) {

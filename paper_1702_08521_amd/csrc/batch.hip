@@ -26,10 +26,27 @@ __device__ __forceinline__ void kadd(KSum& a, double x) {
 // items[i] = (run, spatial cell); one wavefront per item.  Each lane sums
 // its strided share of the velocity row (compensated), then the lanes are
 // combined by a fixed shuffle tree, so the result does not depend on timing.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double vsum(mf4 v) {
+  return ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+}
+__device__ __forceinline__ double vsum(md2 v) { return v.x + v.y; }
+template <typename T>
+struct MVec {
+  typedef mf4 type;
+};
+template <>
+struct MVec<double> {
+  typedef md2 type;
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) batch_moment_kernel(const BatchRun* __restrict__ runs,
                                                            const int2* __restrict__ items,
                                                            int nitems) {
+  using V = typename MVec<T>::type;
+  constexpr int VN = 16 / sizeof(T);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   for (int it = blockIdx.x * 4 + wave; it < nitems; it += gridDim.x * 4) {
@@ -38,15 +55,30 @@ __global__ void __launch_bounds__(256) batch_moment_kernel(const BatchRun* __res
     const T* b = reinterpret_cast<const T*>(r.f) + (int64_t)item.y * r.nvs;
     KSum acc{0.0, 0.0};
     constexpr int U = 4;
-    int64_t k = lane;
-    for (; k + (U - 1) * 64 < r.nvs; k += U * 64) {
-      T x[U];
+    if (r.nvs % VN == 0) {
+      // 16-byte vectors; a vector's components are added in double first
+      const V* bv = reinterpret_cast<const V*>(b);
+      const int64_t nv = r.nvs / VN;
+      int64_t k = lane;
+      for (; k + (U - 1) * 64 < nv; k += U * 64) {
+        V x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = b[k + u * 64];
+        for (int u = 0; u < U; ++u) x[u] = bv[k + u * 64];
 #pragma unroll
-      for (int u = 0; u < U; ++u) kadd(acc, (double)x[u]);
+        for (int u = 0; u < U; ++u) kadd(acc, vsum(x[u]));
+      }
+      for (; k < nv; k += 64) kadd(acc, vsum(bv[k]));
+    } else {
+      int64_t k = lane;
+      for (; k + (U - 1) * 64 < r.nvs; k += U * 64) {
+        T x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = b[k + u * 64];
+#pragma unroll
+        for (int u = 0; u < U; ++u) kadd(acc, (double)x[u]);
+      }
+      for (; k < r.nvs; k += 64) kadd(acc, (double)b[k]);
     }
-    for (; k < r.nvs; k += 64) kadd(acc, (double)b[k]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const double os = __shfl_down(acc.s, off, 64);

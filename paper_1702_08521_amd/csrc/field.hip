@@ -51,14 +51,77 @@ __device__ KSum block_ksum(KSum v) {
 
 // rho[ix] = dvol * sum over the contiguous velocity block of cell ix.
 // One workgroup per spatial cell; fixed reduction order (deterministic).
+// When the block is a whole number of 16-byte vectors, each thread reads
+// vectors (four loads in flight), adds a vector's components in double and
+// feeds the sum to one of two compensated accumulators.
+template <typename T>
+struct MomVec;
+template <>
+struct MomVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int N = 4;
+  __device__ static double sum(type v) {
+    return ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+  }
+};
+template <>
+struct MomVec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int N = 2;
+  __device__ static double sum(type v) { return v.x + v.y; }
+};
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) moment_kernel(const T* __restrict__ f, int64_t nvs,
                                                     double dvol, double* __restrict__ rho) {
+  using MV = MomVec<T>;
+  using V = typename MV::type;
   const T* b = f + (int64_t)blockIdx.x * nvs;
-  KSum acc{0.0, 0.0};
-  for (int64_t k = threadIdx.x; k < nvs; k += NT) kadd(acc, (double)b[k]);
-  KSum tot = block_ksum<NT>(acc);
+  KSum acc0{0.0, 0.0}, acc1{0.0, 0.0};
+  if (nvs % MV::N == 0) {
+    const V* bv = reinterpret_cast<const V*>(b);
+    const int64_t nv = nvs / MV::N;
+    constexpr int U = 4;
+    int64_t k = threadIdx.x;
+    for (; k + (U - 1) * NT < nv; k += U * NT) {
+      V x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = bv[k + u * NT];
+#pragma unroll
+      for (int u = 0; u < U; u += 2) {
+        kadd(acc0, MV::sum(x[u]));
+        kadd(acc1, MV::sum(x[u + 1]));
+      }
+    }
+    for (; k < nv; k += NT) kadd(acc0, MV::sum(bv[k]));
+  } else {
+    for (int64_t k = threadIdx.x; k < nvs; k += NT) kadd(acc0, (double)b[k]);
+  }
+  kmerge(acc0, acc1);
+  KSum tot = block_ksum<NT>(acc0);
   if (threadIdx.x == 0) rho[blockIdx.x] = dvol * (tot.s + tot.c);
+}
+
+// rho[i * ncol + c] = dvol * sum_q part[(c * nsub + q) * n + i]; thread
+// (c, i) adds the nsub tile-row sums of its cell in tile order (compensated).
+__global__ void __launch_bounds__(256) moment_reduce_kernel(const double* __restrict__ part, int n,
+                                                            int64_t ncol, int64_t nsub, double dvol,
+                                                            double* __restrict__ rho) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ncol * n) return;
+  const int64_t c = g / n;
+  const int i = (int)(g - c * n);
+  const double* p = part + c * nsub * n + i;
+  KSum acc0{0.0, 0.0}, acc1{0.0, 0.0};
+  int64_t q = 0;
+  for (; q + 1 < nsub; q += 2) {
+    const double x0 = p[q * n], x1 = p[(q + 1) * n];
+    kadd(acc0, x0);
+    kadd(acc1, x1);
+  }
+  if (q < nsub) kadd(acc0, p[q * n]);
+  kmerge(acc0, acc1);
+  rho[(int64_t)i * ncol + c] = dvol * (acc0.s + acc0.c);
 }
 
 // ---- discrete Fourier transform along one axis ------------------------
@@ -267,6 +330,15 @@ hipError_t launch_moment(int dtype, const void* f, int64_t nxs, int64_t nvs, dou
   else
     hipLaunchKernelGGL((moment_kernel<float, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
                        (const float*)f, nvs, dvol, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_reduce(const double* part, int n, int64_t ncol, int64_t nsub, double dvol,
+                                double* rho, hipStream_t s) {
+  const int64_t total = ncol * n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(moment_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     part, n, ncol, nsub, dvol, rho);
   return hipGetLastError();
 }
 

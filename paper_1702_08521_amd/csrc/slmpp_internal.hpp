@@ -36,6 +36,8 @@ struct SweepArgs {
   int32_t bc;           // SLMPP_BC_*
   int32_t cmode;        // SpeedMode
   int32_t nfast;        // integer shifts |N| <= nfast read the LDS tile directly
+  double* mom;          // non-null: per-tile sums of the result over each tile row
+                        // (fast strided 64-pencil tiles only), mom[tile * n + i]
 };
 
 // Tiling of one sweep launch: W pencils per tile, S segments per pencil,
@@ -116,6 +118,11 @@ constexpr size_t kBatchTileLdsMax = 96 * 1024;
 // ---- field kernels (field.hip) ----
 hipError_t launch_moment(int dtype, const void* f, int64_t nxs, int64_t nvs, double dvol,
                          double* rho, hipStream_t s);
+// rho[i * ncol + c] = dvol * sum_{q < nsub} part[(c * nsub + q) * n + i]: the
+// velocity moment from the row sums of a fused x_1 sweep (ncol spatial
+// columns of x_2..x_D, nsub tiles per velocity block).
+hipError_t launch_moment_reduce(const double* part, int n, int64_t ncol, int64_t nsub, double dvol,
+                                double* rho, hipStream_t s);
 hipError_t launch_poisson(const double* rho, double* phi, double* accel, double2* bufA,
                           double2* bufB, const double2* twiddles, const int64_t* tw_off,
                           const double* green, int D, const int64_t* nx, const double* h,

@@ -258,6 +258,12 @@ struct Vec<double> {
 
 // scatter / gather the components of a 16-byte vector to / from
 // consecutive elements (component access keeps the vector in registers)
+// sum of a vector's components in double (fused moment)
+__device__ __forceinline__ double vsum(const vf4& v) {
+  return ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+}
+__device__ __forceinline__ double vsum(const vd2& v) { return v.x + v.y; }
+
 __device__ __forceinline__ void put(float* d, const vf4& v) {
   d[0] = v.x;
   d[1] = v.y;
@@ -575,7 +581,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
 // W divides `inner` (strided) or inner == 1 (contiguous), RC divides n,
 // VN divides RC (and n when contiguous), and all pencil / cell counts of a
 // block fit in 32 bits.
-template <typename T, int ORDER, int RC, int WT, bool CONTIG>
+template <typename T, int ORDER, int RC, int WT, bool CONTIG, bool MOM>
 __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan pl,
                                                          const PencilEntry<T>* __restrict__ table) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -743,6 +749,28 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
         *reinterpret_cast<V*>(f + gbase + goff0 + k * gstep) = v;
       }
     }
+    if constexpr (MOM) {
+      // fused velocity moment (strided 64-pencil tiles within one velocity
+      // block): four lanes per tile row each add a quarter of the row's 64
+      // pencils in double (16-byte reads, start rotated by the row so the
+      // lanes of a wavefront hit distinct LDS banks), then the four partial
+      // sums are combined in a fixed order and stored per tile and row
+      static_assert(!CONTIG && WT == 64, "fused moment needs strided 64-pencil tiles");
+      const int q = tid & 3;
+      for (int i = tid >> 2; i < n; i += nthr >> 2) {
+        const T* row = tile + (i + G) * W;
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16 / VN; ++r) {
+          V x;
+          get(row + ((q * 16 + r * VN + 4 * i) & 63), x);
+          v += vsum(x);
+        }
+        v += __shfl_xor(v, 1, 4);
+        v += __shfl_xor(v, 2, 4);
+        if (q == 0) a.mom[t * n + i] = v;
+      }
+    }
     __syncthreads();
   }
 }
@@ -820,9 +848,9 @@ hipError_t launch_k(const SweepArgs& a, const SweepPlan& p, const void* table, h
   return hipGetLastError();
 }
 
-template <typename T, int ORDER, int RC, int WT, bool CONTIG>
+template <typename T, int ORDER, int RC, int WT, bool CONTIG, bool MOM = false>
 hipError_t launch_fast(const SweepArgs& a, const SweepPlan& p, const void* table, hipStream_t s) {
-  auto kern = sweep_fast_kernel<T, ORDER, RC, WT, CONTIG>;
+  auto kern = sweep_fast_kernel<T, ORDER, RC, WT, CONTIG, MOM>;
   if (p.lds_bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -852,7 +880,9 @@ hipError_t launch_w(const SweepArgs& a, const SweepPlan& p, const void* table, h
   if (p.fast) {
     if (a.inner == 1) return launch_fast<T, ORDER, RC, 64, true>(a, p, table, s);
     switch (p.W) {
-      case 64: return launch_fast<T, ORDER, RC, 64, false>(a, p, table, s);
+      case 64:
+        if (a.mom) return launch_fast<T, ORDER, RC, 64, false, true>(a, p, table, s);
+        return launch_fast<T, ORDER, RC, 64, false>(a, p, table, s);
       case 48: return launch_fast<T, ORDER, RC, 48, false>(a, p, table, s);
       case 32: return launch_fast<T, ORDER, RC, 32, false>(a, p, table, s);
       default: break;
