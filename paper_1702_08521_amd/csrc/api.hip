@@ -293,7 +293,7 @@ struct slmpp_ctx {
     hipError_t e = tic(5, 0.0, 0.0);
     if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, s, table(), tcount, stream);
     if (e == hipSuccess) e = toc();
-    const int cls = inner == 1 ? 1 : (p.W == 64 ? 0 : 4);
+    const int cls = inner == 1 ? 1 : (s.mom ? 6 : (p.W == 64 ? 0 : 4));
     if (e == hipSuccess) e = tic(cls, 2.0 * cells * esize(), cells);
     if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
     if (e == hipSuccess) e = toc();

@@ -20,9 +20,9 @@ OK, ERR_INVALID, ERR_SHAPE, ERR_NONFINITE, ERR_WORKSPACE, ERR_DEVICE, ERR_STATE 
 F64, F32 = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_NONE, LIM_MP, LIM_MPP = 0, 1, 2
-TIMING_CLASSES = 6
+TIMING_CLASSES = 7
 TIMING_NAMES = ("sweep_strided_w64", "sweep_contiguous", "moment", "poisson",
-                "sweep_strided_other", "pencil_table")
+                "sweep_strided_other", "pencil_table", "sweep_strided_w64_moment")
 
 
 class SlmppError(RuntimeError):

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert slmpp.lib().slmpp_abi_version() == 1
+    assert slmpp.lib().slmpp_abi_version() == 2
 
 
 def _desc(**kw):
