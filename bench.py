@@ -201,8 +201,8 @@ def main():
                     help="oracle steps of the whole ensemble in its cpu_baseline (--workload ensemble)")
     ap.add_argument("--ensemble-steps", type=int, default=100,
                     help="steps of the batched ensemble reported in detail.ensemble (0: skip)")
-    ap.add_argument("--fp64-compare", type=int, default=3,
-                    help="steps of the same workload in FP64 storage for the FP32-vs-FP64 line (0: skip)")
+    ap.add_argument("--fp64-compare", type=int, default=1,
+                    help="1: run the same workload in FP64 storage for its rate and the FP32 error (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -232,6 +232,7 @@ def main():
     ctx.init_f_separable(s, gv)
     ctx.field()
     ctx.sync()
+    diag0 = ctx.diag()
     log("[bench] initialised")
     if args.warmup > 0:
         ctx.step(dt, args.warmup)
@@ -309,29 +310,55 @@ def main():
         "detail": {"per_class": per_class, "mass": diag["mass"], "f_min": diag["f_min"],
                    "nonfinite": diag["nonfinite"]},
     }
-    ctx.close()
-    del ctx
-    torch.cuda.empty_cache()
-
     if args.fp64_compare > 0 and storage == slmpp.F32:
-        # the same workload with FP64 storage on the same GPU
+        # the same workload from the same start with FP64 storage on the same
+        # GPU: its rate, and the error of FP32 storage after the same steps
+        total = args.warmup + args.steps
         ctx64 = slmpp.Context(slmpp.make_desc(spec, slmpp.F64), stream=stream, device=dev)
         ctx64.init_f_separable(s, gv)
         ctx64.field()
+        d64_0 = ctx64.diag()
         ctx64.step(dt, 1)
         ctx64.sync()
+        n64 = max(total - 1, 1)
         t0 = time.perf_counter()
-        ctx64.step(dt, args.fp64_compare)
+        ctx64.step(dt, n64)
         ctx64.sync()
         e64 = time.perf_counter() - t0
+        d64 = ctx64.diag()
+        num = torch.zeros((), dtype=torch.float64, device=dev)
+        den = torch.zeros((), dtype=torch.float64, device=dev)
+        a32 = ctx.f.reshape(-1)
+        a64 = ctx64.f.reshape(-1)
+        chunk = 1 << 27
+        with torch.cuda.stream(stream):
+            for c0 in range(0, cells, chunk):
+                x = a32[c0:c0 + chunk].double()
+                y = a64[c0:c0 + chunk]
+                num += (x - y).abs().sum()
+                den += y.abs().sum()
+                del x
+        stream.synchronize()
         out["detail"]["fp64_same_workload"] = {
-            "steps": args.fp64_compare,
-            "cell_updates_per_s": sweeps * cells * args.fp64_compare / e64,
-            "ms_per_step": e64 / args.fp64_compare * 1e3,
+            "steps": n64,
+            "cell_updates_per_s": sweeps * cells * n64 / e64,
+            "ms_per_step": e64 / n64 * 1e3,
         }
+        out["detail"]["fp32_vs_fp64"] = {
+            "steps": total,
+            "l1_rel": (num / den).item(),
+            "mass_drift_f32": abs(diag["mass"] - diag0["mass"]) / abs(diag0["mass"]),
+            "mass_drift_f64": abs(d64["mass"] - d64_0["mass"]) / abs(d64_0["mass"]),
+            "field_energy_rel_diff": abs(diag["field_energy"] - d64["field_energy"]) / abs(d64["field_energy"]),
+            "mode_amp_rel_diff": abs(diag["mode_amp"] - d64["mode_amp"]) / abs(d64["mode_amp"]),
+        }
+        log(f"[bench] fp32 vs fp64 after {total} steps: {out['detail']['fp32_vs_fp64']}")
+        del a32, a64
         ctx64.close()
         del ctx64
-        torch.cuda.empty_cache()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
 
     if args.ensemble_steps > 0 and storage == slmpp.F32:
         out["detail"]["ensemble"] = ensemble_leg(args.ensemble_steps, 5, "f32", compare_fp64=True)
