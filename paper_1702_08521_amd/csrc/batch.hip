@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) batch_moment_kernel(const BatchRun* __res
       for (; k + (U - 1) * 64 < nv; k += U * 64) {
         V x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = bv[k + u * 64];
+        for (int u = 0; u < U; ++u) x[u] = __builtin_nontemporal_load(bv + k + u * 64);
 #pragma unroll
         for (int u = 0; u < U; ++u) kadd(acc, vsum(x[u]));
       }
