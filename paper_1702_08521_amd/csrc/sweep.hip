@@ -131,10 +131,10 @@ __device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T u_plus, T u_minu
 
 // Interface flux at the face between processing positions m and m+1
 // (upwind cell m).  q holds r_{m-3}..r_{m+3} (seventh order) or
-// r_{m-2}..r_{m+2} (fifth order).  d_m and DM_{m-1/2} come from the
-// previous face; d_{m+1} and DM_{m+1/2} are returned for the next one.
+// r_{m-2}..r_{m+2} (fifth order); the MP constraint works on the five
+// cells r_{m-2}..r_{m+2} in both cases.
 template <typename T, int ORDER, int LIM>
-__device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha, T& d_m, T& dm_prev) {
+__device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha) {
   constexpr int o = (ORDER == 7) ? 1 : 0;  // offset of the MP stencil in q
   T phi = w[0] * q[0];
 #pragma unroll
@@ -142,20 +142,27 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha, T&
   if constexpr (LIM == SLMPP_LIM_NONE) {
     return phi;
   } else {
-    const T fm1 = q[o + 1], f0 = q[o + 2], fp1 = q[o + 3], fp2 = q[o + 4];
-    // App. A steps 4-7 (the early accept of step 3 is implied: a value
-    // strictly between f_i and f* already lies in [f^min, f^max])
-    const T d_new = vfma(T(-2), fp1, f0 + fp2);
-    const T dm_new = minmod4(vfma(T(4), d_m, -d_new), vfma(T(4), d_new, -d_m), d_m, d_new);
+    const T fm2 = q[o], fm1 = q[o + 1], f0 = q[o + 2], fp1 = q[o + 3], fp2 = q[o + 4];
     const T slope = f0 - fm1;
-    const T f_ul = vfma(alpha, slope, f0);
-    const T f_md = vfma(T(-0.5), dm_new, T(0.5) * (f0 + fp1));
-    const T f_lc = vfma(T(4.0 / 3.0), dm_prev, vfma(T(0.5), slope, f0));
-    const T lo = vmax(min3(f0, fp1, f_md), min3(f0, f_ul, f_lc));
-    const T hi = vmin(max3(f0, fp1, f_md), max3(f0, f_ul, f_lc));
-    T phib = med3(phi, lo, hi);
-    d_m = d_new;
-    dm_prev = dm_new;
+    // App. A steps 2-3: a value strictly between f_i and f* is accepted
+    const T fstar = f0 + minmod2(fp1 - f0, alpha * slope);
+    const bool accept = (phi - f0) * (phi - fstar) < T(0);
+    T phib = phi;
+    // steps 4-7, skipped when every lane of the wavefront accepted (the
+    // common case on smooth data: about half of the VALU work per cell)
+    if (!__all(accept)) {
+      const T dm1 = vfma(T(-2), fm1, fm2 + f0);
+      const T d0 = vfma(T(-2), f0, fm1 + fp1);
+      const T dp1 = vfma(T(-2), fp1, f0 + fp2);
+      const T dm4_plus = minmod4(vfma(T(4), d0, -dp1), vfma(T(4), dp1, -d0), d0, dp1);
+      const T dm4_minus = minmod4(vfma(T(4), dm1, -d0), vfma(T(4), d0, -dm1), dm1, d0);
+      const T f_ul = vfma(alpha, slope, f0);
+      const T f_md = vfma(T(-0.5), dm4_plus, T(0.5) * (f0 + fp1));
+      const T f_lc = vfma(T(4.0 / 3.0), dm4_minus, vfma(T(0.5), slope, f0));
+      const T lo = vmax(min3(f0, fp1, f_md), min3(f0, f_ul, f_lc));
+      const T hi = vmin(max3(f0, fp1, f_md), max3(f0, f_ul, f_lc));
+      phib = accept ? phi : med3(phi, lo, hi);
+    }
     if constexpr (LIM == SLMPP_LIM_MPP) {
       // PP limiter, Sec. 2.1.1: keep both half-updates non-negative
       const T u_plus = vfma(-tz, phib, f0);
@@ -211,18 +218,14 @@ __device__ __forceinline__ void advance(const T* __restrict__ col, int stride, i
   T q[WIN];
 #pragma unroll
   for (int k = 0; k < WIN; ++k) q[k] = fetch();
-  constexpr int o = (ORDER == 7) ? 1 : 0;
-  T d_prev = vfma(T(-2), q[o + 1], q[o] + q[o + 2]);   // d_{m0-2}
-  T d_m = vfma(T(-2), q[o + 2], q[o + 1] + q[o + 3]);  // d_{m0-1}
-  T dm_prev = minmod4(vfma(T(4), d_prev, -d_m), vfma(T(4), d_m, -d_prev), d_prev, d_m);
-  T f_left = face_flux<T, ORDER, LIM>(q, w, tz, alpha, d_m, dm_prev);
+  T f_left = face_flux<T, ORDER, LIM>(q, w, tz, alpha);
   if constexpr (RC > 0) {
 #pragma unroll
     for (int k = 0; k < RC; ++k) {
 #pragma unroll
       for (int j = 0; j < WIN - 1; ++j) q[j] = q[j + 1];
       q[WIN - 1] = fetch();
-      const T f_right = face_flux<T, ORDER, LIM>(q, w, tz, alpha, d_m, dm_prev);
+      const T f_right = face_flux<T, ORDER, LIM>(q, w, tz, alpha);
       out[k] = vfma(-z, f_right - f_left, q[H]);
       f_left = f_right;
     }
@@ -232,7 +235,7 @@ __device__ __forceinline__ void advance(const T* __restrict__ col, int stride, i
 #pragma unroll
       for (int j = 0; j < WIN - 1; ++j) q[j] = q[j + 1];
       q[WIN - 1] = fetch();
-      const T f_right = face_flux<T, ORDER, LIM>(q, w, tz, alpha, d_m, dm_prev);
+      const T f_right = face_flux<T, ORDER, LIM>(q, w, tz, alpha);
       *optr = vfma(-z, f_right - f_left, q[H]);
       optr += step;
       f_left = f_right;
