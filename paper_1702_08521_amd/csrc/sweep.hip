@@ -374,6 +374,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
   constexpr int KB = 6;
   const bool vec_strided = block && (W % VN) == 0 && (a.inner % VN) == 0 && (gbase % VN) == 0 &&
                            (nthr % (W / VN)) == 0;
+  // strided periodic tiles with G <= n fill their ghost rows while staging
+  // (the generic strided path needs every pencil column loaded: nthr % W == 0)
+  const bool wrap_rows = !contiguous && periodic && G <= n && (vec_strided || (nthr % W) == 0);
   if (contiguous) {
     const int total = wv * n;
     if ((n % VN) == 0) {
@@ -421,9 +424,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
         if (ib + k * di < n)
           buf[k] = __builtin_nontemporal_load(reinterpret_cast<const V*>(gp + k * gstep));
 #pragma unroll
-      for (int k = 0; k < KB; ++k)
-        if (ib + k * di < n)
-          *reinterpret_cast<V*>(tile + (ib + k * di + G) * W + c * VN) = buf[k];
+      for (int k = 0; k < KB; ++k) {
+        if (ib + k * di < n) {
+          const int i = ib + k * di;
+          V* dst = reinterpret_cast<V*>(tile + (i + G) * W + c * VN);
+          *dst = buf[k];
+          if (wrap_rows) {
+            if (i < G) *reinterpret_cast<V*>(tile + (i + G + n) * W + c * VN) = buf[k];
+            if (i >= n - G) *reinterpret_cast<V*>(tile + (i + G - n) * W + c * VN) = buf[k];
+          }
+        }
+      }
     }
   } else {
     // generic strided tile: thread -> fixed pencil column, rows stepped
@@ -439,8 +450,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
         for (int k = 0; k < KB; ++k)
           if (ib + k * di < n) buf[k] = gp[(int64_t)(ib + k * di) * a.inner];
 #pragma unroll
-        for (int k = 0; k < KB; ++k)
-          if (ib + k * di < n) tile[(ib + k * di + G) * W + jj] = buf[k];
+        for (int k = 0; k < KB; ++k) {
+          if (ib + k * di < n) {
+            const int i = ib + k * di;
+            tile[(i + G) * W + jj] = buf[k];
+            if (wrap_rows) {
+              if (i < G) tile[(i + G + n) * W + jj] = buf[k];
+              if (i >= n - G) tile[(i + G - n) * W + jj] = buf[k];
+            }
+          }
+        }
       }
     }
   }
@@ -452,7 +471,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
     }
   }
   const bool safe = __syncthreads_or(need_safe) != 0;
-  if (periodic && G > 0) {
+  if (periodic && G > 0 && !wrap_rows) {
     for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
       const int g = e2 / W, jj = e2 - g * W;
       const int pr = g < G ? g - G : n + (g - G);  // physical cell of the ghost
@@ -638,6 +657,10 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
     goff0 = (int64_t)i0 * inner + c * VN;
     gstep = (int64_t)S * VN * inner;
   }
+  // strided periodic tiles with G <= n fill their ghost rows while staging
+  const bool wrap_rows = !CONTIG && periodic && G <= n;
+  int i0s = 0;  // first physical row of this thread's vectors (strided)
+  if constexpr (!CONTIG) i0s = tid / (W / VN);
   // zero ghost cells once: interior writes never touch them
   if (!periodic) {
     for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
@@ -701,11 +724,23 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
       }
     }
     // ---- prefetched data -> LDS ----
+    // (strided periodic tiles also write the first and last G rows into the
+    // ghost rows on the other side, which saves a copy pass and a barrier)
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      if (vlim[k] < wv) put(tile + loff[k], pf[k]);
+    for (int k = 0; k < NV; ++k) {
+      if (vlim[k] < wv) {
+        put(tile + loff[k], pf[k]);
+        if constexpr (!CONTIG) {
+          if (wrap_rows) {
+            const int i = i0s + k * S * VN;  // physical row of vector k
+            if (i < G) put(tile + loff[k] + n * W, pf[k]);
+            if (i >= n - G) put(tile + loff[k] - n * W, pf[k]);
+          }
+        }
+      }
+    }
     const bool safe = __syncthreads_or(need_safe) != 0;
-    if (periodic) {
+    if (periodic && !wrap_rows) {
       for (int e2 = tid; e2 < 2 * G * W; e2 += nthr) {
         const int g = e2 / W, c = e2 - g * W;
         const int pr = g < G ? g - G : n + (g - G);
