@@ -103,13 +103,13 @@ typedef struct {
 
 /* Per-kernel-class timing gathered with HIP events on the context stream. */
 #define SLMPP_TIMING_CLASSES 7 /* 0: sweeps along a strided axis, tiles of
-                                     64 pencils,
+                                     128 pencils,
                                   1: sweeps along the contiguous axis,
                                   2: velocity moment, 3: Poisson + force,
                                   4: sweeps along a strided axis, other tiles,
                                   5: per-pencil shift / weight tables,
                                   6: x_1 sweeps of slmpp_step that also sum
-                                     the velocity moment (64-pencil tiles) */
+                                     the velocity moment                 */
 typedef struct {
   int64_t launches[SLMPP_TIMING_CLASSES];
   double total_ms[SLMPP_TIMING_CLASSES];  /* summed kernel durations       */

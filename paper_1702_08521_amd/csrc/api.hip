@@ -69,7 +69,8 @@ Layout layout_of(const slmpp_grid_desc& d) {
   L.table = take(pencil_table_bytes(SLMPP_F64, std::max<int64_t>(maxnv, nxs)));
   L.stage_doubles = std::max<int64_t>(std::min<int64_t>(kStageChunk, ncell), nxs + sumnv);
   L.stage = take(sizeof(double) * L.stage_doubles);
-  // row sums of the x_1 sweep's 64-pencil tiles (fused velocity moment)
+  // row sums of the x_1 sweep's tiles (fused velocity moment; 64 or 128
+  // pencils per tile)
   L.mom_doubles = ncell / 64;
   L.mom = take(sizeof(double) * std::max<int64_t>(L.mom_doubles, 1));
   L.total = off;
@@ -181,6 +182,7 @@ struct slmpp_ctx {
   double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
   void* table() { return work + lay.table; }
   double* mom() { return reinterpret_cast<double*>(work + lay.mom); }
+  int mom_w = 64;  // tile width of the last fused x_1 sweep
   size_t esize() const { return d.storage == SLMPP_F64 ? 8 : 4; }
 
   slmpp_status fail(slmpp_status code, const char* fmt, ...) {
@@ -283,9 +285,10 @@ struct slmpp_ctx {
     SweepPlan p = plan_sweep(d.storage, d.order, d.limiter, s.n, s.npen, inner, s.nfast);
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
-    if (fuse_moment && a == 0 && p.fast && p.W == 64 && inner > 1 && nvs % 64 == 0 &&
-        p.tiles * (int64_t)s.n <= lay.mom_doubles) {
+    if (fuse_moment && a == 0 && p.fast && (p.W == 64 || p.W == 128) && inner > 1 &&
+        nvs % p.W == 0 && p.tiles * (int64_t)s.n <= lay.mom_doubles) {
       s.mom = mom();
+      mom_w = p.W;
       if (fused) *fused = true;
     }
     const double cells = (double)ncell;
@@ -293,7 +296,7 @@ struct slmpp_ctx {
     hipError_t e = tic(5, 0.0, 0.0);
     if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, s, table(), tcount, stream);
     if (e == hipSuccess) e = toc();
-    const int cls = inner == 1 ? 1 : (s.mom ? 6 : (p.W == 64 ? 0 : 4));
+    const int cls = inner == 1 ? 1 : (s.mom ? 6 : (p.W == 128 ? 0 : 4));
     if (e == hipSuccess) e = tic(cls, 2.0 * cells * esize(), cells);
     if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
     if (e == hipSuccess) e = toc();
@@ -326,7 +329,7 @@ struct slmpp_ctx {
     double dvol = 1.0;
     for (int l = 0; l < D; ++l) dvol *= hv[l];
     const int n = (int)d.nx[0];
-    const int64_t ncol = nxs / n, nsub = nvs / 64;
+    const int64_t ncol = nxs / n, nsub = nvs / mom_w;
     hipError_t e = tic(2, 8.0 * (double)ncol * nsub * n + 8.0 * nxs, 0.0);
     if (e == hipSuccess) e = launch_moment_reduce(mom(), n, ncol, nsub, dvol, rho(), stream);
     if (e == hipSuccess) e = toc();

@@ -796,24 +796,26 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
       }
     }
     if constexpr (MOM) {
-      // fused velocity moment (strided 64-pencil tiles within one velocity
-      // block): four lanes per tile row each add a quarter of the row's 64
-      // pencils in double (16-byte reads, start rotated by the row so the
-      // lanes of a wavefront hit distinct LDS banks), then the four partial
-      // sums are combined in a fixed order and stored per tile and row
-      static_assert(!CONTIG && WT == 64, "fused moment needs strided 64-pencil tiles");
-      const int q = tid & 3;
-      for (int i = tid >> 2; i < n; i += nthr >> 2) {
+      // fused velocity moment (strided tiles of 64 or 128 pencils within
+      // one velocity block): LPR lanes per tile row each add 16 of the
+      // row's pencils in double (16-byte reads, start rotated by the row so
+      // the lanes of a wavefront spread over the LDS banks), then the
+      // partial sums are combined in a fixed order and stored per tile and
+      // row
+      static_assert(!CONTIG && (WT == 64 || WT == 128), "fused moment needs wide strided tiles");
+      constexpr int LPR = WT / 16;
+      const int q = tid % LPR;
+      for (int i = tid / LPR; i < n; i += nthr / LPR) {
         const T* row = tile + (i + G) * W;
         double v = 0.0;
 #pragma unroll
         for (int r = 0; r < 16 / VN; ++r) {
           V x;
-          get(row + ((q * 16 + r * VN + 4 * i) & 63), x);
+          get(row + ((q * 16 + r * VN + 4 * i) & (WT - 1)), x);
           v += vsum(x);
         }
-        v += __shfl_xor(v, 1, 4);
-        v += __shfl_xor(v, 2, 4);
+#pragma unroll
+        for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, LPR);
         if (q == 0) a.mom[t * n + i] = v;
       }
     }
@@ -926,6 +928,9 @@ hipError_t launch_w(const SweepArgs& a, const SweepPlan& p, const void* table, h
   if (p.fast) {
     if (a.inner == 1) return launch_fast<T, ORDER, RC, 64, true>(a, p, table, s);
     switch (p.W) {
+      case 128:
+        if (a.mom) return launch_fast<T, ORDER, RC, 128, false, true>(a, p, table, s);
+        return launch_fast<T, ORDER, RC, 128, false>(a, p, table, s);
       case 64:
         if (a.mom) return launch_fast<T, ORDER, RC, 64, false, true>(a, p, table, s);
         return launch_fast<T, ORDER, RC, 64, false>(a, p, table, s);
@@ -1125,16 +1130,32 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
   };
   // W: pencils per tile.  Strided tiles should not straddle a block of
   // `inner` pencils, so W divides inner when a divisor in the list exists.
+  // Wider tiles read longer contiguous runs of each row (128 pencils: 512 B
+  // in FP32), which the strided x sweeps need; a width is taken only when
+  // some compile-time segment length fits it.
+  auto has_r = [&](int Wc) {
+    for (int c : {12, 16, 24})
+      if (n % c == 0 && Wc * (n / c) <= 256) return true;
+    return false;
+  };
   int W = 0;
   if (W_override > 0) {
     W = W_override;
   } else if (contiguous) {
     W = 64;
   } else {
-    for (int c : {64, 48, 32, 16}) {
-      if (inner % c == 0) {
+    for (int c : {128, 64, 48, 32, 16}) {
+      if (inner % c == 0 && has_r(c)) {
         W = c;
         break;
+      }
+    }
+    if (W == 0) {
+      for (int c : {64, 48, 32, 16}) {
+        if (inner % c == 0) {
+          W = c;
+          break;
+        }
       }
     }
     if (W == 0) W = 64;
@@ -1170,7 +1191,7 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
                       (int64_t)n * W < ((int64_t)1 << 24);
   p.fast = R > 0 && R % vn == 0 && fits32 && W_override == 0 &&
            (contiguous ? (W == 64 && n % vn == 0) : (inner % W == 0 && inner % vn == 0 &&
-                                                     (W == 64 || W == 48 || W == 32)));
+                                                     (W == 128 || W == 64 || W == 48 || W == 32)));
   if (p.fast) p.lds_bytes = lds(W, true);
   return p;
 }

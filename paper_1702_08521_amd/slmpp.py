@@ -21,8 +21,8 @@ F64, F32 = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_NONE, LIM_MP, LIM_MPP = 0, 1, 2
 TIMING_CLASSES = 7
-TIMING_NAMES = ("sweep_strided_w64", "sweep_contiguous", "moment", "poisson",
-                "sweep_strided_other", "pencil_table", "sweep_strided_w64_moment")
+TIMING_NAMES = ("sweep_strided_w128", "sweep_contiguous", "moment", "poisson",
+                "sweep_strided_other", "pencil_table", "sweep_x1_moment")
 
 
 class SlmppError(RuntimeError):
