@@ -75,8 +75,8 @@ typedef struct {
   int32_t order;         /* 5 (CSL5 / MP5) or 7 (CSL7 / MP7)                  */
   int32_t limiter;       /* slmpp_limiter                                     */
   int32_t poisson_order; /* 2, 4 or 6: Green function and FDA order (App. C)  */
-  int64_t nx[3];         /* cells per spatial axis, 1..65536                  */
-  int64_t nv[3];         /* cells per velocity axis, 1..65536                 */
+  int64_t nx[3];         /* cells per spatial axis, 1..4096                   */
+  int64_t nv[3];         /* cells per velocity axis, 1..4096                  */
   double x_lo[3], x_hi[3]; /* spatial domain, cell centres at lo+(i+1/2)dx    */
   double v_lo[3], v_hi[3]; /* velocity domain                                 */
   double alpha;          /* MP parameter (App. A: alpha = 4), > 0             */
@@ -87,8 +87,18 @@ typedef struct {
                             field solve is periodic in space                */
   int32_t storage;       /* slmpp_dtype of f (sweeps compute in this type;
                             moment, Poisson and forces are always double)   */
-  int32_t flags;         /* must be 0                                        */
+  int32_t flags;         /* 0 or SLMPP_FLAG_RK3                              */
 } slmpp_grid_desc;
+
+/* flags: time integration of every sweep by the method of lines with the
+ * MP(P) interface values and the three-stage TVD Runge-Kutta scheme of
+ * Eq. (RK) (RK-MP5/7, RK-MPP5/7, Sec. 2.1.1) instead of the semi-Lagrangian
+ * update.  Each sweep then needs |c dt / h| <= 1 (positivity with the PP
+ * limiter needs < 1/2): sweeps along x_l are checked on the host
+ * (SLMPP_ERR_INVALID); a velocity sweep whose acceleration breaks it writes
+ * NaN into the affected pencils (counted by slmpp_diag).  The workspace
+ * grows by one copy of f.  Not available for batched ensembles. */
+#define SLMPP_FLAG_RK3 1
 
 typedef struct slmpp_ctx slmpp_ctx;
 

@@ -26,6 +26,8 @@ BC_OUTFLOW = 1
 LIM_NONE = 0
 LIM_MP = 1
 LIM_MPP = 2
+TIME_SL = 0
+TIME_RK3 = 1
 
 
 def build(native: bool = False) -> str:
@@ -55,6 +57,8 @@ class Grid(ctypes.Structure):
         ("kappa", ctypes.c_double),
         ("x_bc", ctypes.c_int32),
         ("v_bc", ctypes.c_int32),
+        ("time_scheme", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
     @property
@@ -87,6 +91,7 @@ def make_grid(spec) -> Grid:
     g.kappa = float(spec.get("kappa", -1.0))
     g.x_bc = int(spec.get("x_bc", BC_PERIODIC))
     g.v_bc = int(spec.get("v_bc", BC_OUTFLOW))
+    g.time_scheme = TIME_RK3 if spec.get("time", "sl") == "rk3" else TIME_SL
     return g
 
 
@@ -115,8 +120,10 @@ def lib():
             "oracle_xi": (_D, [_D, _D, _D]),
             "oracle_sweep_pencil": (None, [_P, _I64, _I64, _D, _I, _I, _D, _I]),
             "oracle_sweep_lines": (None, [_P, _I64, _I64, _I64, _D, _I, _I, _D, _I]),
-            "oracle_advect_x": (None, [ctypes.POINTER(Grid), _P, _I, _D]),
-            "oracle_advect_v": (None, [ctypes.POINTER(Grid), _P, _I, _D, _P]),
+            "oracle_rk_pencil": (_I, [_P, _I64, _I64, _D, _I, _I, _D, _I]),
+            "oracle_rk_interp": (_D, [_P, _I]),
+            "oracle_advect_x": (_I, [ctypes.POINTER(Grid), _P, _I, _D]),
+            "oracle_advect_v": (_I, [ctypes.POINTER(Grid), _P, _I, _D, _P]),
             "oracle_density_moment": (None, [ctypes.POINTER(Grid), _P, _P]),
             "oracle_poisson_solve": (None, [ctypes.POINTER(Grid), _P, _P, _P]),
             "oracle_field": (None, [ctypes.POINTER(Grid), _P, _P]),
@@ -189,6 +196,23 @@ def sweep_pencil(g, xi_, order=5, limiter=LIM_MPP, alpha=4.0, bc=BC_PERIODIC):
     return a
 
 
+def rk_interp(stencil, order):
+    """f^int_{i-1/2} of the RK-MP schemes from f_{i-3..i+1} (order 5) or
+    f_{i-4..i+2} (order 7)."""
+    s = _f64(stencil)
+    assert s.size == order
+    return lib().oracle_rk_interp(_ptr(s), order)
+
+
+def rk_pencil(g, nu, order=5, limiter=LIM_MPP, alpha=4.0, bc=BC_PERIODIC):
+    """Return the pencil g after one RK-MP(P) step (TVD-RK3, Sec. 2.1.1)
+    with CFL number nu = c dt / h (|nu| <= 1)."""
+    a = _f64(g).copy()
+    if lib().oracle_rk_pencil(_ptr(a), a.size, 1, nu, order, limiter, alpha, bc) != 0:
+        raise ValueError("RK time integration needs |nu| <= 1")
+    return a
+
+
 def sweep_lines(f, axis, xi_, order=5, limiter=LIM_MPP, alpha=4.0, bc=BC_PERIODIC):
     """All pencils of the C-contiguous float64 array f along `axis`, in place."""
     assert f.dtype == np.float64 and f.flags.c_contiguous
@@ -200,13 +224,15 @@ def sweep_lines(f, axis, xi_, order=5, limiter=LIM_MPP, alpha=4.0, bc=BC_PERIODI
 
 
 def advect_x(grid, f, dim, dt):
-    lib().oracle_advect_x(ctypes.byref(grid), _ptr(f), dim, dt)
+    if lib().oracle_advect_x(ctypes.byref(grid), _ptr(f), dim, dt) != 0:
+        raise ValueError("RK time integration needs |c dt / h| <= 1")
     return f
 
 
 def advect_v(grid, f, dim, dt, accel_component):
     a = _f64(accel_component)
-    lib().oracle_advect_v(ctypes.byref(grid), _ptr(f), dim, dt, _ptr(a))
+    if lib().oracle_advect_v(ctypes.byref(grid), _ptr(f), dim, dt, _ptr(a)) != 0:
+        raise ValueError("RK time integration needs |c dt / h| <= 1")
     return f
 
 

@@ -39,6 +39,11 @@
  *       spacings).
  *   R7  Four-point FDA: the printed difference has the opposite sign of
  *       the derivative; the derivative itself is used here.
+ *   R8  RK-MP(P)5/7 (Sec. 2.1.1).  Each TVD-RK stage recomputes the
+ *       interface values from the stage data extended by the boundary
+ *       condition (as R5); c < 0 reverses the pencil as in R2.  The PP
+ *       limiter is the Sec. 2.1.1 one with the CFL number nu of the step.
+ *       |nu| <= 1 is required (no integer shift exists in this scheme).
  */
 #include <math.h>
 #include <stdint.h>
@@ -63,7 +68,12 @@ typedef struct {
   double alpha;       /* MP parameter (App. A uses 4) */
   double kappa;       /* Poisson coupling: lap(phi) = kappa * rho */
   int32_t x_bc, v_bc;
+  int32_t time_scheme; /* ORACLE_TIME_SL or ORACLE_TIME_RK3 */
+  int32_t pad;
 } oracle_grid;
+
+#define ORACLE_TIME_SL 0  /* semi-Lagrangian update, Eq. (SL)          */
+#define ORACLE_TIME_RK3 1 /* method of lines + three-stage TVD-RK, Eq. (RK) */
 
 /* ------------------------------------------------------------------ */
 /* Scalar pieces of the interface flux                                 */
@@ -275,6 +285,90 @@ void oracle_sweep_pencil(double* g, int64_t n, int64_t stride, double xi, int or
   free(work);
 }
 
+/* Interpolated interface value f^int_{m-1/2} of the MP schemes (the
+ * printed fifth- and seventh-order formulas, Sec. 2.1.1), from the working
+ * pencil r around the upwind cell m-1. */
+static double rk_interp(const double* r, int64_t m, int order) {
+  if (order == 5)
+    return (2.0 * r[m - 3] - 13.0 * r[m - 2] + 47.0 * r[m - 1] + 27.0 * r[m] -
+            3.0 * r[m + 1]) / 60.0;
+  return (-3.0 * r[m - 4] + 25.0 * r[m - 3] - 101.0 * r[m - 2] + 319.0 * r[m - 1] +
+          214.0 * r[m] - 38.0 * r[m + 1] + 4.0 * r[m + 2]) / 420.0;
+}
+
+/* The same interpolation on a stencil s = f_{i-3..i+1} (fifth order) or
+ * f_{i-4..i+2} (seventh order): f^int_{i-1/2}. */
+double oracle_rk_interp(const double* s, int order) {
+  return rk_interp(s + (order == 5 ? 3 : 4), 0, order);
+}
+
+/* L_m(u) = fhat_{m+1/2} - fhat_{m-1/2} for m = 0 .. n-1 of the working
+ * pencil u (n values, extended by the boundary condition into r), with
+ * fbar = MP(f^int) and fhat = PP(fbar; u_{m-1}, u_m) (Sec. 2.1.1). */
+static void rk_operator(const double* u, int64_t n, int order, int limiter, double alpha,
+                        int bc, double nu, double* r, double* F, double* L) {
+  for (int64_t m = -ORACLE_GHOST; m < n + ORACLE_GHOST; ++m)
+    r[m] = extended(u, n, 1, m, bc);
+  for (int64_t m = 0; m <= n; ++m) {
+    double phi = rk_interp(r, m, order);
+    if (limiter >= ORACLE_LIM_MP)
+      phi = oracle_mp(phi, r[m - 3], r[m - 2], r[m - 1], r[m], r[m + 1], alpha);
+    if (limiter >= ORACLE_LIM_MPP) phi = oracle_pp(phi, r[m - 1], r[m], nu);
+    F[m] = phi;
+  }
+  for (int64_t m = 0; m < n; ++m) L[m] = F[m + 1] - F[m];
+}
+
+/* One RK-MP(P) step of a single pencil with CFL number nu = c dt / h,
+ * Eq. (RK):  f1 = f - nu L(f),  f2 = 3/4 f + 1/4 (f1 - nu L(f1)),
+ * f^{n+1} = 1/3 f + 2/3 (f2 - nu L(f2)).  `work` needs
+ * ORACLE_RK_WORK(n) doubles.  Returns -1 (and leaves g) when |nu| > 1. */
+#define ORACLE_RK_WORK(n) (6 * ((n) + 2 * ORACLE_GHOST) + 1)
+int oracle_rk_pencil_work(double* g, int64_t n, int64_t stride, double xi, int order,
+                          int limiter, double alpha, int bc, double* work) {
+  if (n <= 0) return 0;
+  if (!(fabs(xi) <= 1.0)) return -1;
+  const int mirror = xi < 0.0; /* reading R8 (as R2) */
+  const double nu = mirror ? -xi : xi;
+  const int64_t span = n + 2 * ORACLE_GHOST;
+  double* u0 = work;               /* f^n in working orientation */
+  double* u1 = work + span;        /* stage values               */
+  double* L = work + 2 * span;
+  double* F = work + 3 * span;
+  double* r = work + 4 * span + ORACLE_GHOST;
+  for (int64_t m = 0; m < n; ++m) u0[m] = g[(mirror ? (n - 1 - m) : m) * stride];
+  /* stage 1 */
+  rk_operator(u0, n, order, limiter, alpha, bc, nu, r, F, L);
+  for (int64_t m = 0; m < n; ++m) u1[m] = u0[m] - nu * L[m];
+  /* stage 2 */
+  rk_operator(u1, n, order, limiter, alpha, bc, nu, r, F, L);
+  for (int64_t m = 0; m < n; ++m) u1[m] = 0.75 * u0[m] + 0.25 * (u1[m] - nu * L[m]);
+  /* stage 3 */
+  rk_operator(u1, n, order, limiter, alpha, bc, nu, r, F, L);
+  for (int64_t m = 0; m < n; ++m) {
+    const double out = u0[m] / 3.0 + 2.0 / 3.0 * (u1[m] - nu * L[m]);
+    g[(mirror ? (n - 1 - m) : m) * stride] = out;
+  }
+  return 0;
+}
+
+int oracle_rk_pencil(double* g, int64_t n, int64_t stride, double xi, int order, int limiter,
+                     double alpha, int bc) {
+  double* work = (double*)malloc(sizeof(double) * ORACLE_RK_WORK(n));
+  int rc = oracle_rk_pencil_work(g, n, stride, xi, order, limiter, alpha, bc, work);
+  free(work);
+  return rc;
+}
+
+/* One sweep of a pencil with the time scheme of the grid. */
+static int scheme_pencil(const oracle_grid* gr, double* g, int64_t n, int64_t stride, double xi,
+                         int bc, double* work) {
+  if (gr->time_scheme == ORACLE_TIME_RK3)
+    return oracle_rk_pencil_work(g, n, stride, xi, gr->order, gr->limiter, gr->alpha, bc, work);
+  oracle_sweep_pencil_work(g, n, stride, xi, gr->order, gr->limiter, gr->alpha, bc, work);
+  return 0;
+}
+
 /* All pencils of an array viewed as [outer][n][inner], same xi for all. */
 void oracle_sweep_lines(double* f, int64_t outer, int64_t n, int64_t inner,
                         double xi, int order, int limiter, double alpha, int bc) {
@@ -319,7 +413,7 @@ double oracle_cell_center(double lo, double hi, int64_t n, int64_t j) {
 double oracle_xi(double c, double dt, double h) { return (c * dt) / h; }
 
 /* Advection along x_dim with speed v_dim, Eq. (adv_pos). */
-void oracle_advect_x(const oracle_grid* g, double* f, int dim, double dt) {
+int oracle_advect_x(const oracle_grid* g, double* f, int dim, double dt) {
   int64_t dims[6];
   grid_dims(g, dims);
   const int nd = 2 * g->D;
@@ -331,25 +425,26 @@ void oracle_advect_x(const oracle_grid* g, double* f, int dim, double dt) {
   const int64_t nvd = g->nv[dim];
   const double h = (g->x_hi[dim] - g->x_lo[dim]) / (double)g->nx[dim];
   const int64_t npen = outer * inner;
-#pragma omp parallel
+  int bad = 0;
+#pragma omp parallel reduction(| : bad)
   {
-    double* work = (double*)malloc(sizeof(double) * (2 * (n + 2 * ORACLE_GHOST) + 1));
+    double* work = (double*)malloc(sizeof(double) * ORACLE_RK_WORK(n));
 #pragma omp for schedule(static)
     for (int64_t p = 0; p < npen; ++p) {
       int64_t o = p / inner, j = p % inner;
       int64_t jv = (j / vstride) % nvd;
       double c = oracle_cell_center(g->v_lo[dim], g->v_hi[dim], nvd, jv);
       double xi = oracle_xi(c, dt, h);
-      oracle_sweep_pencil_work(f + o * n * inner + j, n, inner, xi, g->order,
-                               g->limiter, g->alpha, g->x_bc, work);
+      bad |= scheme_pencil(g, f + o * n * inner + j, n, inner, xi, g->x_bc, work) != 0;
     }
     free(work);
   }
+  return bad ? -1 : 0;
 }
 
 /* Advection along v_dim with speed accel[dim-th component at x],
  * Eq. (adv_vel).  accel holds prod(nx) values for this component. */
-void oracle_advect_v(const oracle_grid* g, double* f, int dim, double dt,
+int oracle_advect_v(const oracle_grid* g, double* f, int dim, double dt,
                      const double* accel) {
   int64_t dims[6];
   grid_dims(g, dims);
@@ -361,19 +456,20 @@ void oracle_advect_v(const oracle_grid* g, double* f, int dim, double dt,
   const int64_t vblock = prod_range(dims, g->D, a); /* v axes before v_dim */
   const double h = (g->v_hi[dim] - g->v_lo[dim]) / (double)g->nv[dim];
   const int64_t npen = outer * inner;
-#pragma omp parallel
+  int bad = 0;
+#pragma omp parallel reduction(| : bad)
   {
-    double* work = (double*)malloc(sizeof(double) * (2 * (n + 2 * ORACLE_GHOST) + 1));
+    double* work = (double*)malloc(sizeof(double) * ORACLE_RK_WORK(n));
 #pragma omp for schedule(static)
     for (int64_t p = 0; p < npen; ++p) {
       int64_t o = p / inner, j = p % inner;
       int64_t ix = o / vblock;
       double xi = oracle_xi(accel[ix], dt, h);
-      oracle_sweep_pencil_work(f + o * n * inner + j, n, inner, xi, g->order,
-                               g->limiter, g->alpha, g->v_bc, work);
+      bad |= scheme_pencil(g, f + o * n * inner + j, n, inner, xi, g->v_bc, work) != 0;
     }
     free(work);
   }
+  return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------ */

@@ -26,7 +26,8 @@ thread_local std::string g_error;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, mom, total;
+  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, mom, rkbuf,
+      total;
   int64_t stage_doubles, mom_doubles;
 };
 
@@ -73,6 +74,8 @@ Layout layout_of(const slmpp_grid_desc& d) {
   // pencils per tile)
   L.mom_doubles = ncell / 64;
   L.mom = take(sizeof(double) * std::max<int64_t>(L.mom_doubles, 1));
+  // TVD-RK time integration keeps f^n of a sweep
+  L.rkbuf = take((d.flags & SLMPP_FLAG_RK3) ? (size_t)ncell * (d.storage == SLMPP_F64 ? 8 : 4) : 0);
   L.total = off;
   return L;
 }
@@ -111,8 +114,8 @@ slmpp_status slmpp::check_grid_desc(const slmpp_grid_desc* d, std::string& msg) 
     msg = "x_bc / v_bc must be SLMPP_BC_PERIODIC or SLMPP_BC_OUTFLOW";
     return SLMPP_ERR_INVALID;
   }
-  if (d->flags != 0) {
-    msg = "flags must be 0";
+  if ((d->flags & ~SLMPP_FLAG_RK3) != 0) {
+    msg = "flags must be 0 or SLMPP_FLAG_RK3";
     return SLMPP_ERR_INVALID;
   }
   if (!is_finite(d->alpha) || !(d->alpha > 0.0) || !is_finite(d->kappa)) {
@@ -182,6 +185,8 @@ struct slmpp_ctx {
   double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
   void* table() { return work + lay.table; }
   double* mom() { return reinterpret_cast<double*>(work + lay.mom); }
+  void* rkbuf() { return work + lay.rkbuf; }
+  bool rk = false;  // SLMPP_FLAG_RK3
   int mom_w = 64;  // tile width of the last fused x_1 sweep
   size_t esize() const { return d.storage == SLMPP_F64 ? 8 : 4; }
 
@@ -237,6 +242,16 @@ struct slmpp_ctx {
     return hipSuccess;
   }
 
+  // TVD-RK needs |v dt / h| <= 1 at every velocity centre of axis l (the
+  // end centres bound it)
+  slmpp_status check_rk_x(int l, double dt) {
+    const double c0 = d.v_lo[l] + 0.5 * hv[l], c1 = d.v_lo[l] + (d.nv[l] - 0.5) * hv[l];
+    const double nu = std::max(std::fabs(c0), std::fabs(c1)) * std::fabs(dt) / hx[l];
+    if (!(nu <= 1.0))
+      return fail(SLMPP_ERR_INVALID, "RK3 time integration needs |v dt / dx| <= 1 (%.3g)", nu);
+    return SLMPP_OK;
+  }
+
   // --- one sweep along array axis a ---
   // fuse_moment (x_1 sweeps only): when the sweep runs as strided 64-pencil
   // tiles lying within velocity blocks, it also leaves per-tile row sums for
@@ -269,6 +284,10 @@ struct slmpp_ctx {
       s.bc = d.x_bc;
       s.xdiv = 1;
       s.nfast = max_shift_velocity(s.vlo, s.dv, s.nvl, dt, s.h, s.n, s.bc);
+      if (rk) {
+        slmpp_status st = check_rk_x(l, dt);
+        if (st != SLMPP_OK) return st;
+      }
     } else {  // v_l sweep, speed a_l(x)
       const int l = a - D;
       int64_t xdiv = 1;
@@ -282,10 +301,14 @@ struct slmpp_ctx {
       s.bc = d.v_bc;
       s.nfast = 4;
     }
+    if (rk) {
+      s.rk = 1;
+      s.nfast = 0;  // no integer shift in an RK stage
+    }
     SweepPlan p = plan_sweep(d.storage, d.order, d.limiter, s.n, s.npen, inner, s.nfast);
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
-    if (fuse_moment && a == 0 && p.fast && (p.W == 64 || p.W == 128) && inner > 1 &&
+    if (fuse_moment && !rk && a == 0 && p.fast && (p.W == 64 || p.W == 128) && inner > 1 &&
         nvs % p.W == 0 && p.tiles * (int64_t)s.n <= lay.mom_doubles) {
       s.mom = mom();
       mom_w = p.W;
@@ -297,9 +320,24 @@ struct slmpp_ctx {
     if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, s, table(), tcount, stream);
     if (e == hipSuccess) e = toc();
     const int cls = inner == 1 ? 1 : (s.mom ? 6 : (p.W == 128 ? 0 : 4));
-    if (e == hipSuccess) e = tic(cls, 2.0 * cells * esize(), cells);
-    if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
-    if (e == hipSuccess) e = toc();
+    if (!rk) {
+      if (e == hipSuccess) e = tic(cls, 2.0 * cells * esize(), cells);
+      if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
+      if (e == hipSuccess) e = toc();
+    } else {
+      // Eq. (RK): f1 = S(f), f2 = 3/4 f + 1/4 S(f1), f^{n+1} = 1/3 f + 2/3 S(f2),
+      // S(u) = u - nu L(u) one stage sweep in place; f^n is kept in rkbuf
+      const size_t bytes = (size_t)ncell * esize();
+      if (e == hipSuccess) e = tic(cls, 14.0 * cells * esize(), 3.0 * cells);
+      if (e == hipSuccess) e = hipMemcpyAsync(rkbuf(), f, bytes, hipMemcpyDeviceToDevice, stream);
+      const double cb[3] = {0.0, 0.75, 1.0 / 3.0}, cf[3] = {1.0, 0.25, 2.0 / 3.0};
+      for (int st = 0; st < 3 && e == hipSuccess; ++st) {
+        e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
+        if (e == hipSuccess && st > 0)
+          e = launch_blend(d.storage, f, rkbuf(), cb[st], cf[st], ncell, stream);
+      }
+      if (e == hipSuccess) e = toc();
+    }
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     return SLMPP_OK;
   }
@@ -423,6 +461,7 @@ slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_d
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->lay = lay;
     c->D = desc->D;
+    c->rk = (desc->flags & SLMPP_FLAG_RK3) != 0;
     for (int l = 0; l < c->D; ++l) {
       c->dims[l] = desc->nx[l];
       c->dims[c->D + l] = desc->nv[l];
@@ -598,6 +637,12 @@ slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
   if (!std::isfinite(dt)) return c->fail(SLMPP_ERR_NONFINITE, "dt is not finite");
   if (nsteps < 1) return c->fail(SLMPP_ERR_INVALID, "nsteps must be >= 1");
   const int D = c->D;
+  if (c->rk) {  // refuse before any work
+    for (int l = 0; l < D; ++l) {
+      slmpp_status st = c->check_rk_x(l, dt);
+      if (st != SLMPP_OK) return st;
+    }
+  }
   for (int32_t it = 0; it < nsteps; ++it) {
     slmpp_status st = SLMPP_OK;
     if (!c->field_valid) st = c->field();

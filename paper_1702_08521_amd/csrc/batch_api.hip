@@ -134,8 +134,8 @@ slmpp_status check_batch(const slmpp_grid_desc* descs, int32_t nruns, std::strin
       msg = "all runs of a batch must share the storage type";
       return SLMPP_ERR_INVALID;
     }
-    if (descs[r].limiter != SLMPP_LIM_MPP) {
-      msg = "batched runs use the SL-MPP limiter";
+    if (descs[r].limiter != SLMPP_LIM_MPP || descs[r].flags != 0) {
+      msg = "batched runs use the SL-MPP scheme (SLMPP_LIM_MPP, flags 0)";
       return SLMPP_ERR_INVALID;
     }
     if (geom_of(descs[r]).nxs > kBatchMaxSpace) {

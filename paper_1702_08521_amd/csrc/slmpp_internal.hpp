@@ -36,6 +36,8 @@ struct SweepArgs {
   int32_t bc;           // SLMPP_BC_*
   int32_t cmode;        // SpeedMode
   int32_t nfast;        // integer shifts |N| <= nfast read the LDS tile directly
+  int32_t rk;           // 1: a TVD-RK stage (interface values at zero Courant
+                        //    number, update with nu = c dt / h, no shift)
   double* mom;          // non-null: per-tile sums of the result over each tile row
                         // (fast strided 64-pencil tiles only), mom[tile * n + i]
 };
@@ -137,6 +139,9 @@ hipError_t launch_diag_f(int dtype, const void* f, int64_t n, double* partials, 
 hipError_t launch_diag_field(const double* accel, int D, int64_t nxs, int64_t nx1, int64_t inner1,
                              double* out, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// f <- cb * b + cf * f over n elements of the storage type (TVD-RK stages)
+hipError_t launch_blend(int dtype, void* f, const void* b, double cb, double cf, int64_t n,
+                        hipStream_t s);
 
 constexpr int kDiagBlocks = 1024;
 

@@ -831,7 +831,12 @@ __device__ __forceinline__ PencilEntry<T> pencil_entry(const SweepArgs& a, int i
   const int n = a.n;
   double zeta;
   int64_t N;
-  if (!(fabs(xi) < 4.0e18)) {  // non-finite or absurd offset: poison the pencil
+  if (a.rk) {
+    // TVD-RK stage (Sec. 2.1.1): no shift, the CFL number itself as zeta;
+    // |nu| > 1 poisons the pencil
+    N = 0;
+    zeta = fabs(xi) <= 1.0 ? xi : __builtin_nan("");
+  } else if (!(fabs(xi) < 4.0e18)) {  // non-finite or absurd offset: poison the pencil
     N = 0;
     zeta = __builtin_nan("");
   } else {
@@ -854,6 +859,9 @@ __device__ __forceinline__ PencilEntry<T> pencil_entry(const SweepArgs& a, int i
   e.base = (int32_t)((mirror ? (int64_t)(n - 1) : 0) - N);
   e.absN = (int32_t)(N < 0 ? -N : N);
   e.z = (T)az;
+  // an RK stage takes the interface interpolation itself: the flux
+  // polynomial at zero Courant number
+  const double zw = a.rk ? 0.0 : az;
 #pragma unroll
   for (int k = 0; k < ORDER; ++k) {
     double acc = 0.0;
@@ -865,7 +873,7 @@ __device__ __forceinline__ PencilEntry<T> pencil_entry(const SweepArgs& a, int i
       } else {
         fr = kCsl5[k][j];
       }
-      acc = acc * az + fr.num / fr.den;
+      acc = acc * zw + fr.num / fr.den;
     }
     e.w[k] = (T)acc;
   }

@@ -20,6 +20,7 @@ OK, ERR_INVALID, ERR_SHAPE, ERR_NONFINITE, ERR_WORKSPACE, ERR_DEVICE, ERR_STATE 
 F64, F32 = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_NONE, LIM_MP, LIM_MPP = 0, 1, 2
+FLAG_RK3 = 1
 TIMING_CLASSES = 7
 TIMING_NAMES = ("sweep_strided_w128", "sweep_contiguous", "moment", "poisson",
                 "sweep_strided_other", "pencil_table", "sweep_x1_moment")
@@ -162,7 +163,7 @@ def make_desc(spec, storage=F64) -> GridDesc:
     d.x_bc = int(spec.get("x_bc", BC_PERIODIC))
     d.v_bc = int(spec.get("v_bc", BC_OUTFLOW))
     d.storage = int(storage)
-    d.flags = 0
+    d.flags = FLAG_RK3 if spec.get("time", "sl") == "rk3" else 0
     return d
 
 

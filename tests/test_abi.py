@@ -50,7 +50,7 @@ def test_workspace_bytes_positive_for_valid_desc():
     ("poisson_order", 3, slmpp.ERR_INVALID),
     ("storage", 2, slmpp.ERR_INVALID),
     ("x_bc", 5, slmpp.ERR_INVALID),
-    ("flags", 1, slmpp.ERR_INVALID),
+    ("flags", 2, slmpp.ERR_INVALID),
     ("alpha", float("nan"), slmpp.ERR_NONFINITE),
     ("alpha", -1.0, slmpp.ERR_NONFINITE),
 ])
@@ -176,3 +176,17 @@ def test_batch_null_handle_calls():
     assert L.slmpp_batch_autotune(None, None) == slmpp.ERR_INVALID
     assert L.slmpp_batch_init_separable(None, 0, None, None, None, None) == slmpp.ERR_INVALID
     assert L.slmpp_batch_tile_width(None, 0, 0) == 0
+
+
+def test_rk_flag_accepted_and_workspace_grows():
+    d = _desc()
+    base = slmpp.workspace_bytes(d)
+    d.flags = slmpp.FLAG_RK3
+    st, _ = slmpp.validate(d)
+    assert st == slmpp.OK
+    ncell = 16 * 32
+    assert slmpp.workspace_bytes(d) >= base + 8 * ncell
+    # batched ensembles use the SL-MPP scheme only
+    e = _ensemble()
+    e[0].flags = slmpp.FLAG_RK3
+    assert slmpp.batch_workspace_bytes(e) == 0

@@ -1,0 +1,158 @@
+"""GPU parity of the RK-MP(P)5/7 time integration (method of lines with
+the three-stage TVD Runge-Kutta scheme, Sec. 2.1.1) against the FP64 oracle.
+
+Single sweeps on seeded random data (every axis class, order, limiter,
+boundary and direction, |nu| up to 0.9), whole Landau runs, and the error
+paths: an x sweep beyond |nu| = 1 is refused on the host, a velocity sweep
+beyond it poisons the affected pencils with NaN.  Tolerances as for the SL
+sweeps: FP64 1e-13 of max|f| per sweep and 1e-12 L1 after 100 steps; FP32
+256 ulps of max|f| per sweep (three stages and two combinations) and 1e-5
+L1 after 100 steps.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1702_08521_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_08521_amd import slmpp
+
+    slmpp.lib()
+    return slmpp
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _stored(f0, storage):
+    return f0.astype(np.float32).astype(np.float64) if storage == 1 else f0.copy()
+
+
+def _ctx(S, spec, storage, f0=None):
+    ctx = S.Context(S.make_desc(spec, storage))
+    if f0 is None:
+        s, gv = W.separable_factors(spec)
+        ctx.init_f_separable(s, gv)
+    else:
+        ctx.init_f_host(f0)
+    return ctx
+
+
+GRIDS = [
+    dict(D=1, nx=[37], nv=[53]),
+    dict(D=1, nx=[130], nv=[70]),
+    dict(D=2, nx=[9, 7], nv=[11, 6]),
+    dict(D=3, nx=[5, 4, 6], nv=[7, 3, 5]),
+    dict(D=2, nx=[48, 48], nv=[48, 48]),  # fast tiles
+]
+
+
+def _spec(g, order, limiter, x_bc, v_bc):
+    D = g["D"]
+    s = W.spec(D, g["nx"], g["nv"], [0.0] * D, [1.0 + 0.1 * l for l in range(D)],
+               [-2.0 - 0.5 * l for l in range(D)], [2.0 + 0.25 * l for l in range(D)],
+               order=order, limiter=limiter, x_bc=x_bc, v_bc=v_bc)
+    s["time"] = "rk3"
+    return s
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+def test_rk_single_sweeps_random(S, storage, order, gi):
+    import torch
+
+    g = GRIDS[gi]
+    limiters = (W.LIM_NONE, W.LIM_MP, W.LIM_MPP) if gi < 4 else (W.LIM_MPP,)
+    for limiter in limiters:
+        for x_bc, v_bc in ((W.BC_PERIODIC, W.BC_OUTFLOW), (W.BC_OUTFLOW, W.BC_PERIODIC)):
+            spec = _spec(g, order, limiter, x_bc, v_bc)
+            grid = O.make_grid(spec)
+            seed = 3000 + 1000 * gi + 100 * order + 10 * limiter + x_bc
+            f0 = _stored(W.random_field(grid.shape, seed), storage)
+            D = g["D"]
+            nxs = int(np.prod(g["nx"]))
+            acc = W.random_accel(nxs, D, seed + 1, scale=1.0)
+            hx = min((spec["x_hi"][l] - spec["x_lo"][l]) / spec["nx"][l] for l in range(D))
+            vmax = max(max(abs(spec["v_lo"][l]), abs(spec["v_hi"][l])) for l in range(D))
+            for dt in (0.45 * hx / vmax, -0.9 * hx / vmax):
+                for axis in range(2 * D):
+                    say(f"case rk grid={gi} dtype={storage} order={order} lim={limiter} "
+                        f"bc=({x_bc},{v_bc}) dt={dt:.4g} axis={axis}")
+                    ctx = _ctx(S, spec, storage, f0)
+                    ref = f0.copy()
+                    if axis < D:
+                        ctx.advect_x(axis, dt)
+                        O.advect_x(grid, ref, axis, dt)
+                    else:
+                        l = axis - D
+                        hv = (spec["v_hi"][l] - spec["v_lo"][l]) / spec["nv"][l]
+                        comp = acc[l * nxs:(l + 1) * nxs] * 0.9 * hv / abs(dt)
+                        ta = torch.tensor(comp, dtype=torch.float64, device="cuda")
+                        ctx.advect_v(l, dt, ta)
+                        O.advect_v(grid, ref, l, dt, comp)
+                    got = ctx.get_f()
+                    ctx.close()
+                    err = np.abs(got - ref).max() / np.abs(ref).max()
+                    tol = 1e-13 if storage == 0 else 256 * 2.0 ** -24
+                    assert err <= tol, (gi, storage, order, limiter, x_bc, dt, axis, err)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_rk_mpp5_landau_100_steps(S, storage):
+    """Linear Landau damping with RK-MPP5 (x-CFL 0.5), 100 steps."""
+    spec = W.landau_1d1v()
+    spec["time"] = "rk3"
+    say(f"case rk landau_1d1v storage={storage}")
+    ctx = _ctx(S, spec, storage)
+    ctx.step(spec["dt"], 100)
+    got = ctx.get_f()
+    d = ctx.diag()
+    ctx.close()
+    f0 = None
+    if storage == 1:
+        s, gv = W.separable_factors(spec)
+        f0 = _stored(O.init_separable(O.make_grid(spec), s, gv), 1)
+    run = O.Run(spec, f0)
+    run.step(spec["dt"], 100)
+    err = float(np.abs(got - run.f).sum() / np.abs(run.f).sum())
+    say(f"  L1 rel {err:.3e}")
+    assert err <= (1e-12 if storage == 0 else 1e-5)
+    assert d["nonfinite"] == 0 and d["f_min"] >= -1e-14 * d["f_max"]
+
+
+def test_rk_error_paths(S):
+    import torch
+
+    spec = W.landau_1d1v(nx=16, nv=32)
+    spec["time"] = "rk3"
+    ctx = _ctx(S, spec, 0)
+    hx = (spec["x_hi"][0] - spec["x_lo"][0]) / 16
+    # the largest velocity centre moves 1.2 cells: refused before any work
+    dt = 1.2 * hx / (6.0 - 6.0 / 32)
+    f_before = ctx.get_f()
+    with pytest.raises(S.SlmppError) as e:
+        ctx.advect_x(0, dt)
+    assert e.value.status == S.ERR_INVALID
+    with pytest.raises(S.SlmppError):
+        ctx.step(dt, 1)
+    assert np.array_equal(ctx.get_f(), f_before)
+    # velocity sweep with |nu| = 1.5 in one spatial cell: that cell's pencil is NaN
+    hv = 12.0 / 32
+    acc = np.zeros(16)
+    acc[3] = 1.5 * hv / 0.1
+    ctx.advect_v(0, 0.1, torch.tensor(acc, dtype=torch.float64, device="cuda"))
+    f = ctx.get_f()
+    assert np.isnan(f[3]).all() and np.isfinite(np.delete(f, 3, axis=0)).all()
+    assert ctx.diag()["nonfinite"] == 32
+    ctx.close()

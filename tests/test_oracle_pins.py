@@ -509,3 +509,121 @@ def test_separability_2d2v_equals_1d1v(oracle):
     r2.step(s1["dt"], 20)
     want = (r1.f / z2)[:, None, :, None] * g2[None, None, None, :]
     assert np.abs(r2.f - want).max() <= 1e-12 * np.abs(want).max()
+
+
+# ---------------------------------------------------------------------------
+# RK-MP(P)5/7: method of lines with the three-stage TVD-RK (Sec. 2.1.1)
+# ---------------------------------------------------------------------------
+def _cell_avg_monomial(k, a, b):
+    return (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a))
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_rk_interpolation_exact_for_polynomials(oracle, order):
+    """f^int_{i-1/2} from cell averages reproduces the point value at the
+    interface for polynomials of degree <= order - 1, and not beyond."""
+    lo = -3 if order == 5 else -4
+    cells = [(lo + j, lo + j + 1) for j in range(order)]  # interface at x = 0
+    for k in range(order + 1):
+        s = [_cell_avg_monomial(k, a, b) for a, b in cells]
+        got = oracle.rk_interp(s, order)
+        want = 1.0 if k == 0 else 0.0
+        if k < order:
+            assert got == pytest.approx(want, abs=1e-12), k
+        else:
+            assert abs(got - want) > 1e-4, k
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_rk_interpolation_is_the_csl_flux_at_zero_courant(oracle, order):
+    """The RK interface value (Sec. 2.1.1) and the CSL flux polynomial
+    (Sec. 2.1.2) at zeta = 0 are the same interpolation."""
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        s = rng.normal(size=order)
+        assert oracle.rk_interp(s, order) == pytest.approx(oracle.csl_flux(s, order, 0.0),
+                                                           rel=1e-13, abs=1e-15)
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_rk_step_is_third_order_taylor_on_a_fourier_mode(oracle, order):
+    """Without limiters the scheme is linear: a Fourier mode is multiplied by
+    1 + a + a^2/2 + a^3/6 with a = -nu * lambda(theta), the TVD-RK property
+    for linear operators, where lambda is the symbol of L built from the
+    oracle's own interpolation."""
+    n, mode, nu = 32, 3, 0.3
+    th = 2 * np.pi * mode / n
+    off = np.arange(order) - (3 if order == 5 else 4)
+    # symbol of f^int_{i-1/2} relative to cell i: sum_k c_k e^{i th off_k}
+    s_re = oracle.rk_interp(np.cos(th * off), order)
+    s_im = oracle.rk_interp(np.sin(th * off), order)
+    interp = s_re + 1j * s_im
+    lam = (np.exp(1j * th) - 1.0) * interp  # fint_{i+1/2} - fint_{i-1/2}
+    a = -nu * lam
+    G = 1 + a + a * a / 2 + a ** 3 / 6
+    j = np.arange(n)
+    for phase in (0.0, 0.7):
+        g = np.cos(th * j + phase)
+        got = oracle.rk_pencil(g, nu, order, oracle.LIM_NONE)
+        want = np.real(G * np.exp(1j * (th * j + phase)))
+        assert np.abs(got - want).max() <= 1e-13
+
+
+def test_rk_mp5_is_fifth_order_at_small_courant(oracle):
+    """Test-1b without PP: RK-MP5 converges at fifth order (nu = 0.05, where
+    the third-order time error of TVD-RK stays below the spatial error)."""
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    errs = []
+    for N in (16, 32, 64, 128):
+        h = 1.0 / N
+        c = (np.arange(N) + 0.5) * h
+        g0 = sum(w * (1 + np.sin(2 * np.pi * (c + 0.5 * h * x))) for x, w in zip(xg, wg)) / 2
+        g = g0.copy()
+        for _ in range(int(round(N / 0.05))):
+            g = oracle.rk_pencil(g, 0.05, 5, oracle.LIM_MP)
+        errs.append(np.abs(g - g0).sum() / np.abs(g0).sum())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert (orders > 4.7).all(), orders
+
+
+def test_rk_quartic_sine_positivity(oracle):
+    """Test-1c at N = 64 to t = 8: RK-MP5 goes negative near the minima,
+    RK-MPP5 does not (Sec. 3.1.3)."""
+    N, nu = 64, 0.4
+    x = (np.arange(N) + 0.5) / N
+    g0 = np.sin(4 * np.pi * x) ** 4
+    a, b = g0.copy(), g0.copy()
+    for _ in range(int(round(8 * N / nu))):
+        a = oracle.rk_pencil(a, nu, 5, oracle.LIM_MP)
+        b = oracle.rk_pencil(b, nu, 5, oracle.LIM_MPP)
+    assert a.min() < -1e-2
+    assert b.min() >= 0.0
+
+
+def test_rk_mpp_positivity_random_pencils(oracle):
+    """RK-MPP keeps f >= 0 for nu < 1/2 (Sec. 2.1.1), on random pencils with
+    zeros and spikes, both orders, both boundary conditions, both signs."""
+    rng = np.random.default_rng(5)
+    for t in range(400):
+        g = W.random_field(40, 100 + t)
+        nu = rng.uniform(-0.49, 0.49)
+        order = 5 if t % 2 else 7
+        bc = oracle.BC_PERIODIC if t % 3 else oracle.BC_OUTFLOW
+        out = oracle.rk_pencil(g, nu, order, oracle.LIM_MPP, bc=bc)
+        assert out.min() >= -1e-14 * g.max(), (t, out.min())
+
+
+def test_rk_conservation_symmetry_and_limits(oracle):
+    rng = np.random.default_rng(8)
+    g = W.random_field(48, 9)
+    for order in (5, 7):
+        for lim in (oracle.LIM_NONE, oracle.LIM_MP, oracle.LIM_MPP):
+            out = oracle.rk_pencil(g, 0.37, order, lim)
+            assert out.sum() == pytest.approx(g.sum(), rel=1e-14)
+            # reflection: a negative speed is the mirrored positive one
+            m = oracle.rk_pencil(g[::-1].copy(), -0.37, order, lim)[::-1]
+            assert np.array_equal(m, out)
+    c = np.full(20, 0.625)
+    assert np.array_equal(oracle.rk_pencil(c, 0.3, 7, oracle.LIM_MPP), c)
+    with pytest.raises(ValueError):
+        oracle.rk_pencil(g, 1.5)
