@@ -199,6 +199,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps of the whole ensemble in its cpu_baseline (--workload ensemble)")
+    ap.add_argument("--rk-compare", type=int, default=2,
+                    help="steps of RK-MPP5 and SL-MPP5 on the same workload (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=100,
                     help="steps of the batched ensemble reported in detail.ensemble (0: skip)")
     ap.add_argument("--fp64-compare", type=int, default=1,
@@ -361,6 +363,31 @@ def main():
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
+
+    if args.rk_compare > 0 and args.workload == "landau_3d3v":
+        # the paper's cost comparison (Sec. 4): RK-MPP5 against SL-MPP5 on the
+        # same 48^3 x 48^3 workload and storage (x-CFL 0.2 suits both)
+        rk = {}
+        for scheme in ("sl", "rk3"):
+            sp = W.landau_3d3v(n=48, order=5)
+            sp["time"] = scheme
+            c = slmpp.Context(slmpp.make_desc(sp, storage), stream=stream, device=dev)
+            c.init_f_separable(*W.separable_factors(sp))
+            c.field()
+            c.step(sp["dt"], 1)
+            c.sync()
+            t0 = time.perf_counter()
+            c.step(sp["dt"], args.rk_compare)
+            c.sync()
+            rk[scheme] = (time.perf_counter() - t0) / args.rk_compare * 1e3
+            c.close()
+            del c
+            torch.cuda.empty_cache()
+        out["detail"]["rk_mpp5_vs_sl_mpp5"] = {
+            "workload": "landau_3d3v 48^3 x 48^3, order 5, same dt", "steps": args.rk_compare,
+            "sl_mpp5_ms_per_step": round(rk["sl"], 2), "rk_mpp5_ms_per_step": round(rk["rk3"], 2),
+            "rk_over_sl": round(rk["rk3"] / rk["sl"], 3)}
+        log(f"[bench] RK-MPP5 vs SL-MPP5: {out['detail']['rk_mpp5_vs_sl_mpp5']}")
 
     if args.ensemble_steps > 0 and storage == slmpp.F32:
         out["detail"]["ensemble"] = ensemble_leg(args.ensemble_steps, 5, "f32", compare_fp64=True)
