@@ -180,6 +180,20 @@ slmpp_status slmpp_advect_v(slmpp_ctx* ctx, int32_t dim, double dt, const double
 /* rho_dev[ix] <- dv^D * sum_v f(ix, v) (compensated double accumulation). */
 slmpp_status slmpp_density_moment(slmpp_ctx* ctx, double* rho_dev);
 
+/* Velocity moments of every spatial cell (Sec. 2.3: density, mean
+ * velocities, velocity dispersions), double, on the device:
+ *   rho_dev[ix]          = dv^D sum_v f(ix, v)            (prod(nx) values)
+ *   mean_dev[l*nxs + ix] = sum_v f v_l / sum_v f          (D*prod(nx))
+ *   disp_dev[l*nxs + ix] = sum_v f (v_l - mean_l)^2 / sum_v f (D*prod(nx))
+ * with v_l the velocity cell centres and nxs = prod(nx); cells with zero
+ * density get zero mean and dispersion.  Compensated accumulation. */
+slmpp_status slmpp_velocity_moments(slmpp_ctx* ctx, double* rho_dev, double* mean_dev,
+                                    double* disp_dev);
+
+/* Velocity distribution F(v) = dx^D sum_x f(x, v) (Sec. 3.3): F_dev gets
+ * prod(nv) doubles on the device, in the layout of one velocity block. */
+slmpp_status slmpp_velocity_distribution(slmpp_ctx* ctx, double* F_dev);
+
 /* Periodic Poisson solve lap(phi) = kappa (rho - mean rho) by discrete
  * Fourier transform with the Green function of order poisson_order
  * (Sec. 2.2), then accel_l = -d(phi)/dx_l by the FDA of the same order

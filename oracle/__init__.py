@@ -125,6 +125,8 @@ def lib():
             "oracle_advect_x": (_I, [ctypes.POINTER(Grid), _P, _I, _D]),
             "oracle_advect_v": (_I, [ctypes.POINTER(Grid), _P, _I, _D, _P]),
             "oracle_density_moment": (None, [ctypes.POINTER(Grid), _P, _P]),
+            "oracle_velocity_moments": (None, [ctypes.POINTER(Grid), _P, _P, _P, _P]),
+            "oracle_velocity_distribution": (None, [ctypes.POINTER(Grid), _P, _P]),
             "oracle_poisson_solve": (None, [ctypes.POINTER(Grid), _P, _P, _P]),
             "oracle_field": (None, [ctypes.POINTER(Grid), _P, _P]),
             "oracle_step": (None, [ctypes.POINTER(Grid), _P, _D, _P]),
@@ -240,6 +242,25 @@ def density_moment(grid, f):
     rho = np.empty(grid.n_space, dtype=np.float64)
     lib().oracle_density_moment(ctypes.byref(grid), _ptr(f), _ptr(rho))
     return rho
+
+
+def velocity_moments(grid, f):
+    """(rho, mean, disp): density, mean velocity and velocity dispersion of
+    every spatial cell (mean, disp: D * prod(nx), component-major)."""
+    n = grid.n_space
+    rho = np.empty(n)
+    mean = np.empty(grid.D * n)
+    disp = np.empty(grid.D * n)
+    lib().oracle_velocity_moments(ctypes.byref(grid), _ptr(f), _ptr(rho), _ptr(mean), _ptr(disp))
+    return rho, mean, disp
+
+
+def velocity_distribution(grid, f):
+    """F(v) = dx^D sum_x f, prod(nv) values."""
+    nvs = int(np.prod(grid.nv[: grid.D]))
+    F = np.empty(nvs)
+    lib().oracle_velocity_distribution(ctypes.byref(grid), _ptr(f), _ptr(F))
+    return F
 
 
 def poisson_solve(grid, rho):

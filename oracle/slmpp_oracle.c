@@ -476,6 +476,89 @@ int oracle_advect_v(const oracle_grid* g, double* f, int dim, double dt,
 /* Velocity moment and field solve                                     */
 /* ------------------------------------------------------------------ */
 
+/* Compensated (Neumaier) accumulator. */
+typedef struct {
+  double s, c;
+} ksum_t;
+static void ksum_add(ksum_t* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+/* Velocity moments of each spatial cell (Sec. 2.3: density, mean
+ * velocities, velocity dispersions):
+ *   rho(x)       = dv^D sum_v f,
+ *   u_l(x)       = dv^D sum_v f v_l / rho,
+ *   sigma2_l(x)  = dv^D sum_v f (v_l - u_l)^2 / rho,
+ * with v_l the cell centres; mean and disp hold D * prod(nx) values
+ * (component-major).  Cells with rho = 0 get u = sigma2 = 0. */
+void oracle_velocity_moments(const oracle_grid* g, const double* f, double* rho, double* mean,
+                             double* disp) {
+  int64_t nxs = 1, nvs = 1;
+  double dvol = 1.0;
+  for (int l = 0; l < g->D; ++l) {
+    nxs *= g->nx[l];
+    nvs *= g->nv[l];
+    dvol *= (g->v_hi[l] - g->v_lo[l]) / (double)g->nv[l];
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t ix = 0; ix < nxs; ++ix) {
+    const double* b = f + ix * nvs;
+    ksum_t s0 = {0, 0}, s1[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t k = 0; k < nvs; ++k) {
+      int64_t rem = k;
+      double v[3] = {0, 0, 0};
+      for (int l = g->D - 1; l >= 0; --l) {
+        const int64_t j = rem % g->nv[l];
+        rem /= g->nv[l];
+        v[l] = oracle_cell_center(g->v_lo[l], g->v_hi[l], g->nv[l], j);
+      }
+      ksum_add(&s0, b[k]);
+      for (int l = 0; l < g->D; ++l) ksum_add(&s1[l], b[k] * v[l]);
+    }
+    const double m0 = s0.s + s0.c;
+    rho[ix] = dvol * m0;
+    double u[3] = {0, 0, 0};
+    for (int l = 0; l < g->D; ++l) u[l] = m0 != 0.0 ? (s1[l].s + s1[l].c) / m0 : 0.0;
+    ksum_t s2[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t k = 0; k < nvs; ++k) {
+      int64_t rem = k;
+      for (int l = g->D - 1; l >= 0; --l) {
+        const int64_t j = rem % g->nv[l];
+        rem /= g->nv[l];
+        const double d = oracle_cell_center(g->v_lo[l], g->v_hi[l], g->nv[l], j) - u[l];
+        ksum_add(&s2[l], b[k] * d * d);
+      }
+    }
+    for (int l = 0; l < g->D; ++l) {
+      mean[l * nxs + ix] = u[l];
+      disp[l * nxs + ix] = m0 != 0.0 ? (s2[l].s + s2[l].c) / m0 : 0.0;
+    }
+  }
+}
+
+/* Velocity distribution F(v) = dx^D sum_x f(x, v) (Sec. 3.3), prod(nv)
+ * values; compensated, in x order. */
+void oracle_velocity_distribution(const oracle_grid* g, const double* f, double* F) {
+  int64_t nxs = 1, nvs = 1;
+  double xvol = 1.0;
+  for (int l = 0; l < g->D; ++l) {
+    nxs *= g->nx[l];
+    nvs *= g->nv[l];
+    xvol *= (g->x_hi[l] - g->x_lo[l]) / (double)g->nx[l];
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < nvs; ++k) {
+    ksum_t s = {0, 0};
+    for (int64_t ix = 0; ix < nxs; ++ix) ksum_add(&s, f[ix * nvs + k]);
+    F[k] = xvol * (s.s + s.c);
+  }
+}
+
 /* rho(x) = Delta v^D * sum_v f, Eq. (poisson); compensated (Neumaier)
  * summation in index order. */
 void oracle_density_moment(const oracle_grid* g, const double* f, double* rho) {

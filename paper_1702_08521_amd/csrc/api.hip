@@ -597,6 +597,28 @@ slmpp_status slmpp_density_moment(slmpp_ctx* c, double* rho_dev) {
   return c->moment(rho_dev);
 }
 
+slmpp_status slmpp_velocity_moments(slmpp_ctx* c, double* rho_dev, double* mean_dev,
+                                    double* disp_dev) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!rho_dev || !mean_dev || !disp_dev)
+    return c->fail(SLMPP_ERR_INVALID, "rho_dev, mean_dev and disp_dev must be non-NULL");
+  hipError_t e = launch_velocity_moments(c->d.storage, c->f, c->D, c->d.nv, c->d.v_lo, c->hv,
+                                         c->nxs, rho_dev, mean_dev, disp_dev, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "velocity moments launch");
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_velocity_distribution(slmpp_ctx* c, double* F_dev) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!F_dev) return c->fail(SLMPP_ERR_INVALID, "F_dev is NULL");
+  double xvol = 1.0;
+  for (int l = 0; l < c->D; ++l) xvol *= c->hx[l];
+  hipError_t e = launch_velocity_distribution(c->d.storage, c->f, c->nxs, c->nvs, xvol, F_dev,
+                                              c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "velocity distribution launch");
+  return SLMPP_OK;
+}
+
 slmpp_status slmpp_poisson_solve(slmpp_ctx* c, const double* rho_dev, double* phi_dev,
                                  double* accel_dev) {
   if (!c) return SLMPP_ERR_INVALID;

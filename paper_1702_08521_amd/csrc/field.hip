@@ -102,6 +102,76 @@ __global__ void __launch_bounds__(NT) moment_kernel(const T* __restrict__ f, int
   if (threadIdx.x == 0) rho[blockIdx.x] = dvol * (tot.s + tot.c);
 }
 
+// Velocity moments of one spatial cell per workgroup (Sec. 2.3): density,
+// mean velocity and dispersion per velocity axis, two passes over the
+// cell's contiguous velocity block (the second re-reads it from cache).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restrict__ f, int D,
+                                                              int64_t nvs, int3 nv, double3 vlo,
+                                                              double3 dv, double dvol, int64_t nxs,
+                                                              double* __restrict__ rho,
+                                                              double* __restrict__ mean,
+                                                              double* __restrict__ disp) {
+  const T* b = f + (int64_t)blockIdx.x * nvs;
+  const int n[3] = {nv.x, nv.y, nv.z};
+  const double lo[3] = {vlo.x, vlo.y, vlo.z}, h[3] = {dv.x, dv.y, dv.z};
+  auto centres = [&](int64_t k, double* v) {
+    int64_t rem = k;
+    for (int l = D - 1; l >= 0; --l) {
+      const int64_t j = rem % n[l];
+      rem /= n[l];
+      v[l] = lo[l] + ((double)j + 0.5) * h[l];
+    }
+  };
+  KSum s0{0.0, 0.0}, s1[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t k = threadIdx.x; k < nvs; k += NT) {
+    double v[3];
+    centres(k, v);
+    const double x = (double)b[k];
+    kadd(s0, x);
+    for (int l = 0; l < D; ++l) kadd(s1[l], x * v[l]);
+  }
+  const KSum t0 = block_ksum<NT>(s0);
+  const double m0 = t0.s + t0.c;
+  double u[3] = {0.0, 0.0, 0.0};
+  for (int l = 0; l < D; ++l) {
+    const KSum t1 = block_ksum<NT>(s1[l]);
+    u[l] = m0 != 0.0 ? (t1.s + t1.c) / m0 : 0.0;
+  }
+  KSum s2[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t k = threadIdx.x; k < nvs; k += NT) {
+    double v[3];
+    centres(k, v);
+    const double x = (double)b[k];
+    for (int l = 0; l < D; ++l) {
+      const double d = v[l] - u[l];
+      kadd(s2[l], x * d * d);
+    }
+  }
+  for (int l = 0; l < D; ++l) {
+    const KSum t2 = block_ksum<NT>(s2[l]);
+    if (threadIdx.x == 0) {
+      mean[(int64_t)l * nxs + blockIdx.x] = u[l];
+      disp[(int64_t)l * nxs + blockIdx.x] = m0 != 0.0 ? (t2.s + t2.c) / m0 : 0.0;
+    }
+  }
+  if (threadIdx.x == 0) rho[blockIdx.x] = dvol * m0;
+}
+
+// F[k] = xvol * sum_x f[x][k]: one thread per velocity cell, rows in x order
+template <typename T>
+__global__ void __launch_bounds__(256) velocity_distribution_kernel(const T* __restrict__ f,
+                                                                    int64_t nxs, int64_t nvs,
+                                                                    double xvol,
+                                                                    double* __restrict__ F) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvs;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    KSum a{0.0, 0.0};
+    for (int64_t ix = 0; ix < nxs; ++ix) kadd(a, (double)f[ix * nvs + k]);
+    F[k] = xvol * (a.s + a.c);
+  }
+}
+
 // rho[i * ncol + c] = dvol * sum_q part[(c * nsub + q) * n + i]; thread
 // (c, i) adds the nsub tile-row sums of its cell in tile order (compensated).
 __global__ void __launch_bounds__(256) moment_reduce_kernel(const double* __restrict__ part, int n,
@@ -452,6 +522,40 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   if (n > 0)
     hipLaunchKernelGGL(copy_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(NT), 0, s,
                        (const uint4*)src, (uint4*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity_moments(int dtype, const void* f, int D, const int64_t* nv,
+                                   const double* vlo, const double* dv, int64_t nxs,
+                                   double* rho, double* mean, double* disp, hipStream_t s) {
+  int64_t nvs = 1;
+  double dvol = 1.0;
+  for (int l = 0; l < D; ++l) {
+    nvs *= nv[l];
+    dvol *= dv[l];
+  }
+  const int3 n3 = make_int3((int)nv[0], D > 1 ? (int)nv[1] : 1, D > 2 ? (int)nv[2] : 1);
+  const double3 lo3 = make_double3(vlo[0], D > 1 ? vlo[1] : 0.0, D > 2 ? vlo[2] : 0.0);
+  const double3 dv3 = make_double3(dv[0], D > 1 ? dv[1] : 1.0, D > 2 ? dv[2] : 1.0);
+  constexpr int NT = 256;
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL((velocity_moments_kernel<double, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
+                       (const double*)f, D, nvs, n3, lo3, dv3, dvol, nxs, rho, mean, disp);
+  else
+    hipLaunchKernelGGL((velocity_moments_kernel<float, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
+                       (const float*)f, D, nvs, n3, lo3, dv3, dvol, nxs, rho, mean, disp);
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity_distribution(int dtype, const void* f, int64_t nxs, int64_t nvs,
+                                        double xvol, double* F, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((nvs + 255) / 256, 4096);
+  if (dtype == SLMPP_F64)
+    hipLaunchKernelGGL(velocity_distribution_kernel<double>, dim3((unsigned)blocks), dim3(256), 0,
+                       s, (const double*)f, nxs, nvs, xvol, F);
+  else
+    hipLaunchKernelGGL(velocity_distribution_kernel<float>, dim3((unsigned)blocks), dim3(256), 0,
+                       s, (const float*)f, nxs, nvs, xvol, F);
   return hipGetLastError();
 }
 

@@ -139,6 +139,12 @@ hipError_t launch_diag_f(int dtype, const void* f, int64_t n, double* partials, 
 hipError_t launch_diag_field(const double* accel, int D, int64_t nxs, int64_t nx1, int64_t inner1,
                              double* out, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// velocity moments per spatial cell and the velocity distribution (double)
+hipError_t launch_velocity_moments(int dtype, const void* f, int D, const int64_t* nv,
+                                   const double* vlo, const double* dv, int64_t nxs,
+                                   double* rho, double* mean, double* disp, hipStream_t s);
+hipError_t launch_velocity_distribution(int dtype, const void* f, int64_t nxs, int64_t nvs,
+                                        double xvol, double* F, hipStream_t s);
 // f <- cb * b + cf * f over n elements of the storage type (TVD-RK stages)
 hipError_t launch_blend(int dtype, void* f, const void* b, double cb, double cf, int64_t n,
                         hipStream_t s);

@@ -94,6 +94,8 @@ SIGNATURES = {
     "slmpp_advect_v": (_S, [_VP, _I32, _D, _VP]),
     "slmpp_density_moment": (_S, [_VP, _VP]),
     "slmpp_poisson_solve": (_S, [_VP, _VP, _VP, _VP]),
+    "slmpp_velocity_moments": (_S, [_VP, _VP, _VP, _VP]),
+    "slmpp_velocity_distribution": (_S, [_VP, _VP]),
     "slmpp_field": (_S, [_VP]),
     "slmpp_field_ptrs": (_S, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
     "slmpp_get_field": (_S, [_VP, _VP, _VP]),
@@ -261,6 +263,15 @@ class Context:
 
     def density_moment(self, rho):
         self._c(lib().slmpp_density_moment(self.h, _VP(rho.data_ptr())))
+
+    def velocity_moments(self, rho, mean, disp):
+        """CUDA float64 tensors of prod(nx), D*prod(nx), D*prod(nx) values."""
+        self._c(lib().slmpp_velocity_moments(self.h, _VP(rho.data_ptr()), _VP(mean.data_ptr()),
+                                             _VP(disp.data_ptr())))
+
+    def velocity_distribution(self, F):
+        """CUDA float64 tensor of prod(nv) values."""
+        self._c(lib().slmpp_velocity_distribution(self.h, _VP(F.data_ptr())))
 
     def poisson_solve(self, rho, accel, phi=None):
         self._c(lib().slmpp_poisson_solve(self.h, _VP(rho.data_ptr()),

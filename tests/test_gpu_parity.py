@@ -338,3 +338,35 @@ def test_fast_tiles_random_sweeps_48(S, storage):
             ctx.close()
             tol = 1e-13 if storage == 0 else 64 * 2.0 ** -24
             assert np.abs(got - ref).max() / np.abs(ref).max() <= tol, (axis, dt)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_velocity_moments_and_distribution(S, storage):
+    """Velocity moments per spatial cell and F(v) against the oracle on the
+    stored values (both accumulate in compensated double)."""
+    import torch
+
+    for gi, g in enumerate(GRIDS):
+        spec = _spec(g, 5, W.LIM_MPP)
+        grid = O.make_grid(spec)
+        f0 = _stored(W.random_field(grid.shape, 40 + gi), storage)
+        f0[tuple(0 for _ in range(g["D"]))] = 0.0  # one cell of zero density
+        say(f"case velocity moments grid={gi} storage={storage}")
+        ctx = _ctx(S, spec, storage, f0)
+        D = g["D"]
+        nxs = int(np.prod(g["nx"]))
+        nvs = int(np.prod(g["nv"]))
+        rho = torch.empty(nxs, dtype=torch.float64, device="cuda")
+        mean = torch.empty(D * nxs, dtype=torch.float64, device="cuda")
+        disp = torch.empty(D * nxs, dtype=torch.float64, device="cuda")
+        F = torch.empty(nvs, dtype=torch.float64, device="cuda")
+        ctx.velocity_moments(rho, mean, disp)
+        ctx.velocity_distribution(F)
+        ctx.sync()
+        ctx.close()
+        r_o, m_o, d_o = O.velocity_moments(grid, f0)
+        F_o = O.velocity_distribution(grid, f0)
+        assert np.abs(rho.cpu().numpy() - r_o).max() <= 1e-14 * np.abs(r_o).max()
+        assert np.abs(mean.cpu().numpy() - m_o).max() <= 1e-13 * max(np.abs(m_o).max(), 1.0)
+        assert np.abs(disp.cpu().numpy() - d_o).max() <= 1e-13 * np.abs(d_o).max()
+        assert np.abs(F.cpu().numpy() - F_o).max() <= 1e-14 * np.abs(F_o).max()

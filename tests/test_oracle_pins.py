@@ -627,3 +627,55 @@ def test_rk_conservation_symmetry_and_limits(oracle):
     assert np.array_equal(oracle.rk_pencil(c, 0.3, 7, oracle.LIM_MPP), c)
     with pytest.raises(ValueError):
         oracle.rk_pencil(g, 1.5)
+
+
+# ---------------------------------------------------------------------------
+# velocity-space diagnostics (Sec. 2.3 moments, Sec. 3.3 F(v))
+# ---------------------------------------------------------------------------
+def test_velocity_moments_of_shifted_maxwellians(oracle):
+    """A shifted, scaled Maxwellian per spatial cell has density n0, mean
+    u0 and dispersion s0^2; on a wide velocity grid the midpoint sums match
+    these to near rounding (the integrand is smooth and decays)."""
+    spec = W.spec(2, [3, 2], [120, 96], [0.0, 0.0], [1.0, 1.0], [-12.0, -10.0], [12.0, 10.0])
+    g = oracle.make_grid(spec)
+    rng = np.random.default_rng(2)
+    n0 = rng.uniform(0.5, 2.0, size=6)
+    u0 = rng.uniform(-1.0, 1.0, size=(2, 6))
+    s0 = rng.uniform(0.7, 1.3, size=(2, 6))
+    v1 = W.centers(-12.0, 12.0, 120)
+    v2 = W.centers(-10.0, 10.0, 96)
+    f = np.empty(g.shape)
+    for ix in range(6):
+        i, j = divmod(ix, 2)
+        a = np.exp(-(v1 - u0[0, ix]) ** 2 / (2 * s0[0, ix] ** 2)) / (np.sqrt(2 * np.pi) * s0[0, ix])
+        b = np.exp(-(v2 - u0[1, ix]) ** 2 / (2 * s0[1, ix] ** 2)) / (np.sqrt(2 * np.pi) * s0[1, ix])
+        f[i, j] = n0[ix] * np.outer(a, b)
+    rho, mean, disp = oracle.velocity_moments(g, f)
+    assert rho == pytest.approx(n0, rel=1e-12)
+    assert mean.reshape(2, 6) == pytest.approx(u0, abs=1e-11)
+    assert disp.reshape(2, 6) == pytest.approx(s0 ** 2, rel=1e-11)
+
+
+def test_velocity_distribution_and_energy_identity(oracle):
+    """F(v) of a separable f = s(x) g(v) is (dx^D sum s) g(v); and the
+    kinetic energy from the moments, sum_x dx^D rho (|u|^2 + sum sigma^2)/2,
+    equals 1/2 sum f |v|^2 dx^D dv^D taken directly."""
+    spec = W.landau_3d3v(n=4, nv=6, order=5, D=2, amp=0.3)
+    g = oracle.make_grid(spec)
+    s, gv = W.separable_factors(spec)
+    f = oracle.init_separable(g, s, gv)
+    F = oracle.velocity_distribution(g, f)
+    dx = np.prod([(spec["x_hi"][l] - spec["x_lo"][l]) / spec["nx"][l] for l in range(2)])
+    dv = np.prod([(spec["v_hi"][l] - spec["v_lo"][l]) / spec["nv"][l] for l in range(2)])
+    assert F == pytest.approx(dx * s.sum() * np.outer(gv[0], gv[1]).ravel(), rel=1e-13)
+    rng = np.random.default_rng(4)
+    fr = W.random_field(g.shape, 12)
+    rho, mean, disp = oracle.velocity_moments(g, fr)
+    nxs = g.n_space
+    k_mom = 0.5 * dx * sum(rho[ix] * sum(mean[l * nxs + ix] ** 2 + disp[l * nxs + ix]
+                                         for l in range(2)) for ix in range(nxs))
+    v1 = W.centers(spec["v_lo"][0], spec["v_hi"][0], spec["nv"][0])
+    v2 = W.centers(spec["v_lo"][1], spec["v_hi"][1], spec["nv"][1])
+    vv = v1[:, None] ** 2 + v2[None, :] ** 2
+    k_dir = 0.5 * dx * dv * float((fr * vv[None, None]).sum())
+    assert k_mom == pytest.approx(k_dir, rel=1e-12)
