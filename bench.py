@@ -199,6 +199,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps of the whole ensemble in its cpu_baseline (--workload ensemble)")
+    ap.add_argument("--merge-compare", type=int, default=6,
+                    help="steps in one call with merged velocity half-steps (0: skip)")
     ap.add_argument("--rk-compare", type=int, default=2,
                     help="steps of RK-MPP5 and SL-MPP5 on the same workload (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=100,
@@ -363,6 +365,28 @@ def main():
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
+
+    if args.merge_compare > 0:
+        # the same workload with merged velocity half-steps (6 instead of 9
+        # sweeps per step for 3D3V within a call)
+        sp = dict(spec, merge_kicks=True)
+        c = slmpp.Context(slmpp.make_desc(sp, storage), stream=stream, device=dev)
+        c.init_f_separable(s, gv)
+        c.field()
+        c.step(dt, 1)
+        c.sync()
+        t0 = time.perf_counter()
+        c.step(dt, args.merge_compare)
+        c.sync()
+        em = (time.perf_counter() - t0) / args.merge_compare * 1e3
+        out["detail"]["merged_kicks"] = {"steps_per_call": args.merge_compare,
+                                         "ms_per_step": round(em, 2),
+                                         "sweeps_per_step": 2 * D,
+                                         "step_speedup": round(out["ms_per_step"] / em, 3)}
+        log(f"[bench] merged kicks: {out['detail']['merged_kicks']}")
+        c.close()
+        del c
+        torch.cuda.empty_cache()
 
     if args.rk_compare > 0 and args.workload == "landau_3d3v":
         # the paper's cost comparison (Sec. 4): RK-MPP5 against SL-MPP5 on the

@@ -87,7 +87,7 @@ typedef struct {
                             field solve is periodic in space                */
   int32_t storage;       /* slmpp_dtype of f (sweeps compute in this type;
                             moment, Poisson and forces are always double)   */
-  int32_t flags;         /* 0 or SLMPP_FLAG_RK3                              */
+  int32_t flags;         /* 0, SLMPP_FLAG_RK3 and/or SLMPP_FLAG_MERGE_KICKS  */
 } slmpp_grid_desc;
 
 /* flags: time integration of every sweep by the method of lines with the
@@ -99,6 +99,14 @@ typedef struct {
  * NaN into the affected pencils (counted by slmpp_diag).  The workspace
  * grows by one copy of f.  Not available for batched ensembles. */
 #define SLMPP_FLAG_RK3 1
+
+/* flags: slmpp_step merges, within one call, the closing velocity
+ * half-step of a step with the opening half-step of the next (they use the
+ * same acceleration) into one velocity sweep with dt: 2D sweeps per step
+ * instead of 3D, plus the first and last half-steps of the call.  The
+ * state after the call is at the same time level; the splitting stays
+ * second order (the result differs from the unmerged one at that order). */
+#define SLMPP_FLAG_MERGE_KICKS 2
 
 typedef struct slmpp_ctx slmpp_ctx;
 

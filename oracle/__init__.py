@@ -58,7 +58,7 @@ class Grid(ctypes.Structure):
         ("x_bc", ctypes.c_int32),
         ("v_bc", ctypes.c_int32),
         ("time_scheme", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("merge_kicks", ctypes.c_int32),
     ]
 
     @property
@@ -92,6 +92,7 @@ def make_grid(spec) -> Grid:
     g.x_bc = int(spec.get("x_bc", BC_PERIODIC))
     g.v_bc = int(spec.get("v_bc", BC_OUTFLOW))
     g.time_scheme = TIME_RK3 if spec.get("time", "sl") == "rk3" else TIME_SL
+    g.merge_kicks = 1 if spec.get("merge_kicks", False) else 0
     return g
 
 
@@ -130,6 +131,7 @@ def lib():
             "oracle_poisson_solve": (None, [ctypes.POINTER(Grid), _P, _P, _P]),
             "oracle_field": (None, [ctypes.POINTER(Grid), _P, _P]),
             "oracle_step": (None, [ctypes.POINTER(Grid), _P, _D, _P]),
+            "oracle_steps": (None, [ctypes.POINTER(Grid), _P, _D, _I64, _P]),
             "oracle_init_separable": (None, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P]),
             "oracle_mass": (_D, [ctypes.POINTER(Grid), _P]),
             "oracle_abi_version": (_I, []),
@@ -308,6 +310,5 @@ class Run:
         self.accel = field(self.grid, self.f)
 
     def step(self, dt, nsteps=1):
-        for _ in range(nsteps):
-            step(self.grid, self.f, dt, self.accel)
+        lib().oracle_steps(ctypes.byref(self.grid), _ptr(self.f), dt, nsteps, _ptr(self.accel))
         return self.f

@@ -69,7 +69,7 @@ typedef struct {
   double kappa;       /* Poisson coupling: lap(phi) = kappa * rho */
   int32_t x_bc, v_bc;
   int32_t time_scheme; /* ORACLE_TIME_SL or ORACLE_TIME_RK3 */
-  int32_t pad;
+  int32_t merge_kicks; /* 1: oracle_steps merges consecutive velocity half-steps */
 } oracle_grid;
 
 #define ORACLE_TIME_SL 0  /* semi-Lagrangian update, Eq. (SL)          */
@@ -733,6 +733,28 @@ void oracle_step(const oracle_grid* g, double* f, double dt, double* accel) {
   for (int l = g->D - 1; l >= 0; --l) oracle_advect_x(g, f, l, dt);
   oracle_field(g, f, accel);
   for (int l = 0; l < g->D; ++l) oracle_advect_v(g, f, l, 0.5 * dt, accel + l * nxs);
+}
+
+/* nsteps Strang steps.  With merge_kicks the closing velocity half-step of
+ * a step and the opening half-step of the next one, which use the same
+ * acceleration, are taken as one velocity step with dt (the splitting of
+ * Eq. (splitting) applied to consecutive steps); the first and the last
+ * half-steps stay halves, so the result is at the same time level. */
+void oracle_steps(const oracle_grid* g, double* f, double dt, int64_t nsteps, double* accel) {
+  if (!g->merge_kicks) {
+    for (int64_t k = 0; k < nsteps; ++k) oracle_step(g, f, dt, accel);
+    return;
+  }
+  if (nsteps <= 0) return;
+  int64_t nxs = 1;
+  for (int l = 0; l < g->D; ++l) nxs *= g->nx[l];
+  for (int l = 0; l < g->D; ++l) oracle_advect_v(g, f, l, 0.5 * dt, accel + l * nxs);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    for (int l = g->D - 1; l >= 0; --l) oracle_advect_x(g, f, l, dt);
+    oracle_field(g, f, accel);
+    const double kick = k + 1 < nsteps ? dt : 0.5 * dt;
+    for (int l = 0; l < g->D; ++l) oracle_advect_v(g, f, l, kick, accel + l * nxs);
+  }
 }
 
 /* f = s(x) * g1(v1) * g2(v2) * g3(v3), the product taken left to right */

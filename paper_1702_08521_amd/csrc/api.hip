@@ -114,8 +114,8 @@ slmpp_status slmpp::check_grid_desc(const slmpp_grid_desc* d, std::string& msg) 
     msg = "x_bc / v_bc must be SLMPP_BC_PERIODIC or SLMPP_BC_OUTFLOW";
     return SLMPP_ERR_INVALID;
   }
-  if ((d->flags & ~SLMPP_FLAG_RK3) != 0) {
-    msg = "flags must be 0 or SLMPP_FLAG_RK3";
+  if ((d->flags & ~(SLMPP_FLAG_RK3 | SLMPP_FLAG_MERGE_KICKS)) != 0) {
+    msg = "flags must combine SLMPP_FLAG_RK3 and SLMPP_FLAG_MERGE_KICKS only";
     return SLMPP_ERR_INVALID;
   }
   if (!is_finite(d->alpha) || !(d->alpha > 0.0) || !is_finite(d->kappa)) {
@@ -664,6 +664,24 @@ slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
       slmpp_status st = c->check_rk_x(l, dt);
       if (st != SLMPP_OK) return st;
     }
+  }
+  if (c->d.flags & SLMPP_FLAG_MERGE_KICKS) {
+    // v(dt/2) [x block, field, v(dt)]... ending with v(dt/2)
+    slmpp_status st = SLMPP_OK;
+    if (!c->field_valid) st = c->field();
+    for (int l = 0; l < D && st == SLMPP_OK; ++l)
+      st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
+    for (int32_t it = 0; it < nsteps && st == SLMPP_OK; ++it) {
+      bool fused = false;
+      for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l)
+        st = c->sweep(l, dt, nullptr, l == 0, &fused);
+      if (st == SLMPP_OK) st = fused ? c->field_from_rowsums() : c->field();
+      const double kick = it + 1 < nsteps ? dt : 0.5 * dt;
+      for (int l = 0; l < D && st == SLMPP_OK; ++l)
+        st = c->sweep(D + l, kick, c->accel() + (int64_t)l * c->nxs);
+    }
+    if (st != SLMPP_OK) c->field_valid = false;
+    return st;
   }
   for (int32_t it = 0; it < nsteps; ++it) {
     slmpp_status st = SLMPP_OK;

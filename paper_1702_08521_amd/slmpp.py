@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_NONE, LIM_MP, LIM_MPP = 0, 1, 2
 FLAG_RK3 = 1
+FLAG_MERGE_KICKS = 2
 TIMING_CLASSES = 7
 TIMING_NAMES = ("sweep_strided_w128", "sweep_contiguous", "moment", "poisson",
                 "sweep_strided_other", "pencil_table", "sweep_x1_moment")
@@ -165,7 +166,8 @@ def make_desc(spec, storage=F64) -> GridDesc:
     d.x_bc = int(spec.get("x_bc", BC_PERIODIC))
     d.v_bc = int(spec.get("v_bc", BC_OUTFLOW))
     d.storage = int(storage)
-    d.flags = FLAG_RK3 if spec.get("time", "sl") == "rk3" else 0
+    d.flags = (FLAG_RK3 if spec.get("time", "sl") == "rk3" else 0) | \
+        (FLAG_MERGE_KICKS if spec.get("merge_kicks", False) else 0)
     return d
 
 

@@ -370,3 +370,16 @@ def test_velocity_moments_and_distribution(S, storage):
         assert np.abs(mean.cpu().numpy() - m_o).max() <= 1e-13 * max(np.abs(m_o).max(), 1.0)
         assert np.abs(disp.cpu().numpy() - d_o).max() <= 1e-13 * np.abs(d_o).max()
         assert np.abs(F.cpu().numpy() - F_o).max() <= 1e-14 * np.abs(F_o).max()
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_merged_kicks_match_oracle(S, storage):
+    """SLMPP_FLAG_MERGE_KICKS: 100 Landau steps (1D1V) and 10 steps of a
+    small 3D3V run in one call each, against the oracle's merged steps."""
+    for spec, n in ((W.landau_1d1v(), 100), (W.landau_3d3v(n=6, nv=8, order=7), 10)):
+        spec["merge_kicks"] = True
+        say(f"case merged kicks {spec['name']} storage={storage} {n} steps")
+        got, ref, _ = _run_pair(S, spec, storage, n)
+        err = l1rel(got, ref)
+        say(f"  L1 rel = {err:.3e}")
+        assert err <= (1e-12 if storage == 0 else 1e-5)

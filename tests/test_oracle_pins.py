@@ -679,3 +679,46 @@ def test_velocity_distribution_and_energy_identity(oracle):
     vv = v1[:, None] ** 2 + v2[None, :] ** 2
     k_dir = 0.5 * dx * dv * float((fr * vv[None, None]).sum())
     assert k_mom == pytest.approx(k_dir, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# merged velocity half-steps across consecutive steps
+# ---------------------------------------------------------------------------
+def test_merged_kicks_single_step_and_free_streaming(oracle):
+    """One step merges nothing (bitwise equal); with no field the velocity
+    sweeps are the identity and merging changes nothing either."""
+    s = W.landau_1d1v(nx=32, nv=64, amp=0.2)
+    a = oracle.Run(s)
+    a.step(s["dt"], 1)
+    m = dict(s, merge_kicks=True)
+    b = oracle.Run(m)
+    b.step(s["dt"], 1)
+    assert np.array_equal(a.f, b.f)
+    free = W.advection_1d1v(32, 16, -2.0, 2.0, "sin4")
+    free["dt"] = 0.01
+    c = oracle.Run(free)
+    c.step(free["dt"], 7)
+    d = oracle.Run(dict(free, merge_kicks=True))
+    d.step(free["dt"], 7)
+    assert np.array_equal(c.f, d.f)
+
+
+def test_merged_kicks_keep_the_landau_rate(oracle):
+    """Test-3 with merged half-steps: the damping rate and frequency still
+    match the dispersion-relation root (the splitting stays second order)."""
+    s = dict(W.landau_1d1v(nx=64, nv=128), merge_kicks=True)
+    run = oracle.Run(s)
+    dt, nx, chunk = s["dt"], 64, 5
+    n = int(round(40.0 / dt)) // chunk
+    # advanced in calls of 5 merged steps; |E_1| is read after each call
+    ts, amp = [0.0], [abs(np.fft.fft(run.accel[:nx])[1])]
+    for k in range(n):
+        run.step(dt, chunk)
+        ts.append((k + 1) * chunk * dt)
+        amp.append(abs(np.fft.fft(run.accel[:nx])[1]))
+    ts, amp = np.array(ts), np.array(amp)
+    pk = [i for i in range(1, len(amp) - 1) if amp[i] > amp[i - 1] and amp[i] >= amp[i + 1]]
+    tp, ap = ts[pk], np.log(amp[pk])
+    sel = (tp > 5) & (tp < 40)
+    gamma = -np.polyfit(tp[sel], ap[sel], 1)[0]
+    assert gamma == pytest.approx(0.15336, rel=0.03)
