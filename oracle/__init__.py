@@ -59,6 +59,8 @@ class Grid(ctypes.Structure):
         ("v_bc", ctypes.c_int32),
         ("time_scheme", ctypes.c_int32),
         ("merge_kicks", ctypes.c_int32),
+        ("isolated", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
     @property
@@ -93,6 +95,7 @@ def make_grid(spec) -> Grid:
     g.v_bc = int(spec.get("v_bc", BC_OUTFLOW))
     g.time_scheme = TIME_RK3 if spec.get("time", "sl") == "rk3" else TIME_SL
     g.merge_kicks = 1 if spec.get("merge_kicks", False) else 0
+    g.isolated = 1 if spec.get("field_bc", "periodic") == "isolated" else 0
     return g
 
 
@@ -130,6 +133,8 @@ def lib():
             "oracle_velocity_distribution": (None, [ctypes.POINTER(Grid), _P, _P]),
             "oracle_poisson_solve": (None, [ctypes.POINTER(Grid), _P, _P, _P]),
             "oracle_field": (None, [ctypes.POINTER(Grid), _P, _P]),
+            "oracle_poisson_isolated": (None, [ctypes.POINTER(Grid), _P, _P, _P]),
+            "oracle_box_inverse_r": (_D, [_D, _D, _D]),
             "oracle_step": (None, [ctypes.POINTER(Grid), _P, _D, _P]),
             "oracle_steps": (None, [ctypes.POINTER(Grid), _P, _D, _I64, _P]),
             "oracle_init_separable": (None, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P]),
@@ -271,6 +276,20 @@ def poisson_solve(grid, rho):
     acc = np.empty(grid.D * grid.n_space, dtype=np.float64)
     lib().oracle_poisson_solve(ctypes.byref(grid), _ptr(r), _ptr(phi), _ptr(acc))
     return phi, acc
+
+
+def poisson_isolated(grid, rho):
+    """(phi, accel) of the isolated-boundary solve (D = 3)."""
+    r = _f64(rho)
+    phi = np.empty(grid.n_space, dtype=np.float64)
+    acc = np.empty(grid.D * grid.n_space, dtype=np.float64)
+    lib().oracle_poisson_isolated(ctypes.byref(grid), _ptr(r), _ptr(phi), _ptr(acc))
+    return phi, acc
+
+
+def box_inverse_r(a, b, c):
+    """Integral of 1/r over the box [-a, a] x [-b, b] x [-c, c]."""
+    return lib().oracle_box_inverse_r(a, b, c)
 
 
 def field(grid, f):

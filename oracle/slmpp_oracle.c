@@ -39,6 +39,13 @@
  *       spacings).
  *   R7  Four-point FDA: the printed difference has the opposite sign of
  *       the derivative; the derivative itself is used here.
+ *   R9  Isolated boundaries (Sec. 2.2, doubling-up method).  The real-
+ *       space Green function is g(r) = -kappa / (4 pi r) (the attractive
+ *       sign for kappa = 4 pi G), sampled at cell-centre separations on the
+ *       grid doubled along each axis with minimum-image distances; at r = 0
+ *       it takes the mean of -kappa / (4 pi r) over one cell.  The forces
+ *       use the FDA on the doubled grid, whose potential beyond the
+ *       physical cells is the isolated potential there.  D = 3 only.
  *   R8  RK-MP(P)5/7 (Sec. 2.1.1).  Each TVD-RK stage recomputes the
  *       interface values from the stage data extended by the boundary
  *       condition (as R5); c < 0 reverses the pencil as in R2.  The PP
@@ -70,6 +77,8 @@ typedef struct {
   int32_t x_bc, v_bc;
   int32_t time_scheme; /* ORACLE_TIME_SL or ORACLE_TIME_RK3 */
   int32_t merge_kicks; /* 1: oracle_steps merges consecutive velocity half-steps */
+  int32_t isolated;    /* 1: isolated-boundary field solve (D = 3) */
+  int32_t pad;
 } oracle_grid;
 
 #define ORACLE_TIME_SL 0  /* semi-Lagrangian update, Eq. (SL)          */
@@ -712,13 +721,103 @@ void oracle_poisson_solve(const oracle_grid* g, const double* rho, double* phi,
   if (!phi) free(ph);
 }
 
+/* Integral of 1/r over the box [-a, a] x [-b, b] x [-c, c] (the potential
+ * of a uniform box at its centre, per unit density): eight times the
+ * octant integral, which has the closed form
+ *   b c asinh(a / sqrt(b^2+c^2)) + a c asinh(b / sqrt(a^2+c^2))
+ *   + a b asinh(c / sqrt(a^2+b^2)) - a^2/2 atan(b c / (a r))
+ *   - b^2/2 atan(a c / (b r)) - c^2/2 atan(a b / (c r)),  r = |(a, b, c)|. */
+double oracle_box_inverse_r(double a, double b, double c) {
+  const double r = sqrt(a * a + b * b + c * c);
+  const double oct = b * c * asinh(a / sqrt(b * b + c * c)) + a * c * asinh(b / sqrt(a * a + c * c)) +
+                     a * b * asinh(c / sqrt(a * a + b * b)) - 0.5 * a * a * atan(b * c / (a * r)) -
+                     0.5 * b * b * atan(a * c / (b * r)) - 0.5 * c * c * atan(a * b / (c * r));
+  return 8.0 * oct;
+}
+
+/* Isolated-boundary field solve (reading R9), D = 3: phi = g * rho by the
+ * DFT of the zero-padded density on the doubled grid, then the forces by
+ * the FDA of order poisson_order on the doubled potential.  phi (may be
+ * NULL) and accel as in oracle_poisson_solve. */
+void oracle_poisson_isolated(const oracle_grid* g, const double* rho, double* phi,
+                             double* accel) {
+  int64_t n[3], m[3], nxs = 1, ms = 1;
+  double h[3];
+  for (int l = 0; l < 3; ++l) {
+    n[l] = g->nx[l];
+    m[l] = 2 * n[l];
+    nxs *= n[l];
+    ms *= m[l];
+    h[l] = (g->x_hi[l] - g->x_lo[l]) / (double)g->nx[l];
+  }
+  double* re = (double*)calloc(ms, sizeof(double));
+  double* im = (double*)calloc(ms, sizeof(double));
+  double* gr = (double*)malloc(sizeof(double) * ms);
+  double* gi = (double*)calloc(ms, sizeof(double));
+  const double vol = h[0] * h[1] * h[2];
+  /* padded density and the Green function times the cell volume */
+  for (int64_t i = 0; i < n[0]; ++i)
+    for (int64_t j = 0; j < n[1]; ++j)
+      for (int64_t k = 0; k < n[2]; ++k)
+        re[(i * m[1] + j) * m[2] + k] = rho[(i * n[1] + j) * n[2] + k];
+  for (int64_t i = 0; i < m[0]; ++i)
+    for (int64_t j = 0; j < m[1]; ++j)
+      for (int64_t k = 0; k < m[2]; ++k) {
+        const int64_t di = i < n[0] ? i : i - m[0];
+        const int64_t dj = j < n[1] ? j : j - m[1];
+        const int64_t dk = k < n[2] ? k : k - m[2];
+        double inv_r;
+        if (di == 0 && dj == 0 && dk == 0)
+          inv_r = oracle_box_inverse_r(0.5 * h[0], 0.5 * h[1], 0.5 * h[2]) / vol;
+        else
+          inv_r = 1.0 / sqrt((di * h[0]) * (di * h[0]) + (dj * h[1]) * (dj * h[1]) +
+                             (dk * h[2]) * (dk * h[2]));
+        gr[(i * m[1] + j) * m[2] + k] = -g->kappa / (4.0 * M_PI) * inv_r * vol;
+      }
+  for (int a = 0; a < 3; ++a) {
+    dft_axis(re, im, m, 3, a, -1);
+    dft_axis(gr, gi, m, 3, a, -1);
+  }
+  for (int64_t q = 0; q < ms; ++q) {
+    const double xr = re[q] * gr[q] - im[q] * gi[q];
+    const double xi = re[q] * gi[q] + im[q] * gr[q];
+    re[q] = xr;
+    im[q] = xi;
+  }
+  for (int a = 0; a < 3; ++a) dft_axis(re, im, m, 3, a, +1);
+  for (int64_t q = 0; q < ms; ++q) re[q] /= (double)ms; /* doubled potential */
+  if (phi)
+    for (int64_t i = 0; i < n[0]; ++i)
+      for (int64_t j = 0; j < n[1]; ++j)
+        for (int64_t k = 0; k < n[2]; ++k)
+          phi[(i * n[1] + j) * n[2] + k] = re[(i * m[1] + j) * m[2] + k];
+  for (int l = 0; l < 3; ++l) {
+    const int64_t inner = prod_range(m, l + 1, 3);
+    for (int64_t i = 0; i < n[0]; ++i)
+      for (int64_t j = 0; j < n[1]; ++j)
+        for (int64_t k = 0; k < n[2]; ++k) {
+          const int64_t q = (i * m[1] + j) * m[2] + k;
+          const int64_t pos = l == 0 ? i : (l == 1 ? j : k);
+          accel[l * nxs + (i * n[1] + j) * n[2] + k] =
+              -fda(re + q - pos * inner, m[l], inner, pos, h[l], g->poisson_order);
+        }
+  }
+  free(re);
+  free(im);
+  free(gr);
+  free(gi);
+}
+
 /* rho then Poisson: acceleration of the current f */
 void oracle_field(const oracle_grid* g, const double* f, double* accel) {
   int64_t nxs = 1;
   for (int l = 0; l < g->D; ++l) nxs *= g->nx[l];
   double* rho = (double*)malloc(sizeof(double) * nxs);
   oracle_density_moment(g, f, rho);
-  oracle_poisson_solve(g, rho, NULL, accel);
+  if (g->isolated)
+    oracle_poisson_isolated(g, rho, NULL, accel);
+  else
+    oracle_poisson_solve(g, rho, NULL, accel);
   free(rho);
 }
 

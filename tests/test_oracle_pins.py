@@ -722,3 +722,74 @@ def test_merged_kicks_keep_the_landau_rate(oracle):
     sel = (tp > 5) & (tp < 40)
     gamma = -np.polyfit(tp[sel], ap[sel], 1)[0]
     assert gamma == pytest.approx(0.15336, rel=0.03)
+
+
+# ---------------------------------------------------------------------------
+# isolated boundaries: doubling-up method (Sec. 2.2)
+# ---------------------------------------------------------------------------
+def test_box_inverse_r_matches_quadrature(oracle):
+    from scipy import integrate
+
+    for a, b, c in ((0.5, 0.5, 0.5), (0.3, 0.7, 0.5), (0.1, 0.2, 0.9)):
+        q, _ = integrate.tplquad(lambda z, y, x: 1.0 / np.sqrt(x * x + y * y + z * z),
+                                 0, a, 0, b, 0, c, epsabs=1e-12, epsrel=1e-12)
+        assert oracle.box_inverse_r(a, b, c) == pytest.approx(8 * q, rel=1e-10)
+
+
+def _iso_grid(oracle, n=(8, 6, 10), order=6):
+    spec = W.spec(3, list(n), [2, 2, 2], [-1.0, -0.6, -1.5], [1.0, 0.9, 1.0], [-1, -1, -1],
+                  [1, 1, 1], kappa=4 * np.pi, poisson_order=order, field_bc="isolated")
+    return spec, oracle.make_grid(spec)
+
+
+def test_isolated_point_mass_is_newtonian(oracle):
+    """A unit mass in one cell (G = 1): the doubled-grid convolution is the
+    direct sum, so phi = -1/r exactly at every other cell (no periodic
+    images), and the cell-mean Green function at the mass itself."""
+    spec, g = _iso_grid(oracle)
+    n = np.array(spec["nx"][:3])
+    h = (np.array(spec["x_hi"][:3]) - np.array(spec["x_lo"][:3])) / n
+    src = (1, 4, 8)  # near the edges: images would show
+    rho = np.zeros(int(n.prod()))
+    rho[np.ravel_multi_index(src, n)] = 1.0 / h.prod()
+    phi, acc = oracle.poisson_isolated(g, rho)
+    idx = np.indices(n).reshape(3, -1).T
+    d = (idx - np.array(src)) * h
+    r = np.sqrt((d * d).sum(1))
+    self_ = r == 0
+    assert np.abs(phi[~self_] + 1.0 / r[~self_]).max() <= 1e-13 * (1.0 / r[~self_]).max()
+    want_self = -oracle.box_inverse_r(*(0.5 * h)) / h.prod()
+    assert phi[self_][0] == pytest.approx(want_self, rel=1e-13)
+    # the force points to the mass and falls off as 1/r^2 (sixth-order FDA,
+    # away from the mass so that no stencil reaches its cell)
+    spec, g = _iso_grid(oracle, n=(16, 16, 16))
+    n = np.array(spec["nx"][:3])
+    h = (np.array(spec["x_hi"][:3]) - np.array(spec["x_lo"][:3])) / n
+    src = (7, 8, 6)
+    rho = np.zeros(int(n.prod()))
+    rho[np.ravel_multi_index(src, n)] = 1.0 / h.prod()
+    _, acc = oracle.poisson_isolated(g, rho)
+    idx = np.indices(n).reshape(3, -1).T
+    d = (idx - np.array(src)) * h
+    r = np.sqrt((d * d).sum(1))
+    a = acc.reshape(3, -1).T
+    far = r >= 6 * h.max()
+    want = -d[far] / r[far, None] ** 3
+    err = np.abs(a[far] - want).max(axis=1) / (1.0 / r[far] ** 2)
+    assert err.max() < 1e-2
+
+
+def test_isolated_solve_is_linear_and_sign_follows_kappa(oracle):
+    spec, g = _iso_grid(oracle, n=(6, 6, 6), order=4)
+    rng = np.random.default_rng(3)
+    r1, r2 = rng.random(216), rng.random(216)
+    p1, a1 = oracle.poisson_isolated(g, r1)
+    p2, a2 = oracle.poisson_isolated(g, r2)
+    p12, a12 = oracle.poisson_isolated(g, 2.0 * r1 + r2)
+    assert np.abs(p12 - (2 * p1 + p2)).max() <= 1e-12 * np.abs(p12).max()
+    assert np.abs(a12 - (2 * a1 + a2)).max() <= 1e-12 * np.abs(a12).max()
+    assert (p1 < 0).all()  # gravity: every cell sees a potential well
+    spec["kappa"] = -1.0
+    ge = oracle.make_grid(spec)
+    pe, _ = oracle.poisson_isolated(ge, r1)
+    assert np.abs(pe + p1 / (4 * np.pi)).max() <= 1e-13 * np.abs(pe).max()
