@@ -42,6 +42,8 @@ def workload(name, dtype):
         return W.landau_nl_1d1v()
     if name == "landau_1d1v":
         return W.landau_1d1v()
+    if name == "collapse_3d3v":
+        return W.collapse_3d3v(nx=64, nv=32, order=5)
     if name == "ensemble":
         return None
     raise SystemExit(f"unknown workload {name}")
@@ -89,7 +91,7 @@ def cpu_baseline(spec_fn, n_sample):
         "cores": threads,
         "kind": "oracle",
         "sample": f"one Strang step ({sweeps} sweeps + moment + Poisson), FP64, "
-                  f"{s['name']} at {n_sample}^{s['D']} x {n_sample}^{s['D']}, {dt:.2f} s",
+                  f"{s['name']} at {s['nx'][0]}^{s['D']} x {s['nv'][0]}^{s['D']}, {dt:.2f} s",
     }
 
 
@@ -442,6 +444,8 @@ def main():
                 return W.landau_3d3v(n=n, order=7)
             if args.workload == "jeans_3d3v":
                 return W.jeans_3d3v(n=n, order=5)
+            if args.workload == "collapse_3d3v":
+                return W.collapse_3d3v(nx=n, nv=n // 2, order=5)
             return workload(args.workload, args.dtype)
 
         out["cpu_baseline"] = cpu_baseline(spec_fn, args.cpu_sample)

@@ -87,7 +87,7 @@ typedef struct {
                             field solve is periodic in space                */
   int32_t storage;       /* slmpp_dtype of f (sweeps compute in this type;
                             moment, Poisson and forces are always double)   */
-  int32_t flags;         /* 0, SLMPP_FLAG_RK3 and/or SLMPP_FLAG_MERGE_KICKS  */
+  int32_t flags;         /* SLMPP_FLAG_* bits (0: none)                     */
 } slmpp_grid_desc;
 
 /* flags: time integration of every sweep by the method of lines with the
@@ -107,6 +107,14 @@ typedef struct {
  * state after the call is at the same time level; the splitting stays
  * second order (the result differs from the unmerged one at that order). */
 #define SLMPP_FLAG_MERGE_KICKS 2
+
+/* flags: the field solve uses isolated boundaries instead of periodic ones
+ * (the doubling-up method of Sec. 2.2: the density is zero-padded to the
+ * grid doubled along each axis and convolved with the real-space Green
+ * function -kappa / (4 pi r); the cell mean of 1/r at r = 0).  Forces by
+ * the FDA of poisson_order on the doubled potential.  D = 3 only; the
+ * workspace grows by 40 doubles per spatial cell. */
+#define SLMPP_FLAG_ISOLATED 4
 
 typedef struct slmpp_ctx slmpp_ctx;
 

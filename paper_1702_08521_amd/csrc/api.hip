@@ -27,7 +27,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, mom, rkbuf,
-      total;
+      isoA, isoB, isoG, tw2, total;
   int64_t stage_doubles, mom_doubles;
 };
 
@@ -76,6 +76,14 @@ Layout layout_of(const slmpp_grid_desc& d) {
   L.mom = take(sizeof(double) * std::max<int64_t>(L.mom_doubles, 1));
   // TVD-RK time integration keeps f^n of a sweep
   L.rkbuf = take((d.flags & SLMPP_FLAG_RK3) ? (size_t)ncell * (d.storage == SLMPP_F64 ? 8 : 4) : 0);
+  // isolated boundaries: two complex buffers and the Green transform on the
+  // doubled grid, twiddles of the doubled axes
+  const bool iso = (d.flags & SLMPP_FLAG_ISOLATED) != 0;
+  const int64_t ms = iso ? 8 * nxs : 0;
+  L.isoA = take(sizeof(double2) * ms);
+  L.isoB = take(sizeof(double2) * ms);
+  L.isoG = take(sizeof(double) * ms);
+  L.tw2 = take(iso ? sizeof(double2) * 2 * sumnx : 0);
   L.total = off;
   return L;
 }
@@ -114,8 +122,12 @@ slmpp_status slmpp::check_grid_desc(const slmpp_grid_desc* d, std::string& msg) 
     msg = "x_bc / v_bc must be SLMPP_BC_PERIODIC or SLMPP_BC_OUTFLOW";
     return SLMPP_ERR_INVALID;
   }
-  if ((d->flags & ~(SLMPP_FLAG_RK3 | SLMPP_FLAG_MERGE_KICKS)) != 0) {
-    msg = "flags must combine SLMPP_FLAG_RK3 and SLMPP_FLAG_MERGE_KICKS only";
+  if ((d->flags & ~(SLMPP_FLAG_RK3 | SLMPP_FLAG_MERGE_KICKS | SLMPP_FLAG_ISOLATED)) != 0) {
+    msg = "flags must combine SLMPP_FLAG_RK3, SLMPP_FLAG_MERGE_KICKS and SLMPP_FLAG_ISOLATED only";
+    return SLMPP_ERR_INVALID;
+  }
+  if ((d->flags & SLMPP_FLAG_ISOLATED) && d->D != 3) {
+    msg = "isolated boundaries need D = 3";
     return SLMPP_ERR_INVALID;
   }
   if (!is_finite(d->alpha) || !(d->alpha > 0.0) || !is_finite(d->kappa)) {
@@ -185,6 +197,12 @@ struct slmpp_ctx {
   double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
   void* table() { return work + lay.table; }
   double* mom() { return reinterpret_cast<double*>(work + lay.mom); }
+  double2* isoA() { return reinterpret_cast<double2*>(work + lay.isoA); }
+  double2* isoB() { return reinterpret_cast<double2*>(work + lay.isoB); }
+  double* isoG() { return reinterpret_cast<double*>(work + lay.isoG); }
+  double2* tw2() { return reinterpret_cast<double2*>(work + lay.tw2); }
+  int64_t tw2_off[3]{};
+  bool isolated = false;  // SLMPP_FLAG_ISOLATED
   void* rkbuf() { return work + lay.rkbuf; }
   bool rk = false;  // SLMPP_FLAG_RK3
   int mom_w = 64;  // tile width of the last fused x_1 sweep
@@ -354,7 +372,10 @@ struct slmpp_ctx {
 
   slmpp_status poisson(const double* rho_dev, double* phi_dev, double* accel_dev) {
     hipError_t e = tic(3, 8.0 * nxs * (2 + D), 0.0);
-    if (e == hipSuccess)
+    if (e == hipSuccess && isolated)
+      e = launch_poisson_isolated(rho_dev, phi_dev ? phi_dev : phi(), accel_dev, isoA(), isoB(),
+                                  tw2(), tw2_off, isoG(), d.nx, hx, d.poisson_order, stream);
+    else if (e == hipSuccess)
       e = launch_poisson(rho_dev, phi_dev ? phi_dev : phi(), accel_dev, bufA(), bufB(), tw(),
                          tw_off, green(), D, d.nx, hx, d.poisson_order, stream);
     if (e == hipSuccess) e = toc();
@@ -422,6 +443,60 @@ slmpp_status slmpp_validate(const slmpp_grid_desc* desc, char* msg, size_t msg_l
   }
   if (st != SLMPP_OK) g_error = m;
   return st;
+}
+
+namespace {
+// Integral of 1/r over the box [-a, a] x [-b, b] x [-c, c]: eight octants
+// with the closed form of the potential of a uniform box at its centre.
+double box_inverse_r(double a, double b, double c) {
+  const double r = std::sqrt(a * a + b * b + c * c);
+  double v = b * c * std::asinh(a / std::sqrt(b * b + c * c));
+  v += a * c * std::asinh(b / std::sqrt(a * a + c * c));
+  v += a * b * std::asinh(c / std::sqrt(a * a + b * b));
+  v -= 0.5 * a * a * std::atan(b * c / (a * r));
+  v -= 0.5 * b * b * std::atan(a * c / (b * r));
+  v -= 0.5 * c * c * std::atan(a * b / (c * r));
+  return 8.0 * v;
+}
+}  // namespace
+
+// Isolated boundaries, doubling-up method (Sec. 2.2): the Green function
+// -kappa / (4 pi r) times the cell volume at the minimum-image separations
+// of the doubled grid (the cell mean of 1/r at r = 0), transformed once.
+hipError_t iso_setup(slmpp_ctx* c, const slmpp_grid_desc& d) {
+  const int64_t m[3] = {2 * d.nx[0], 2 * d.nx[1], 2 * d.nx[2]};
+  const int64_t ms = m[0] * m[1] * m[2];
+  const double h[3] = {c->hx[0], c->hx[1], c->hx[2]};
+  const double vol = h[0] * h[1] * h[2];
+  const double self = box_inverse_r(0.5 * h[0], 0.5 * h[1], 0.5 * h[2]) / vol;
+  std::vector<double2> g(ms);
+  for (int64_t i = 0; i < m[0]; ++i)
+    for (int64_t j = 0; j < m[1]; ++j)
+      for (int64_t k = 0; k < m[2]; ++k) {
+        const double dx = (double)(i < d.nx[0] ? i : i - m[0]) * h[0];
+        const double dy = (double)(j < d.nx[1] ? j : j - m[1]) * h[1];
+        const double dz = (double)(k < d.nx[2] ? k : k - m[2]) * h[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double inv_r = r2 > 0.0 ? 1.0 / std::sqrt(r2) : self;
+        g[(i * m[1] + j) * m[2] + k] = make_double2(-d.kappa / (4.0 * M_PI) * inv_r * vol, 0.0);
+      }
+  std::vector<double2> tw;
+  for (int l = 0; l < 3; ++l) {
+    c->tw2_off[l] = (int64_t)tw.size();
+    for (int64_t q = 0; q < m[l]; ++q) {
+      const double ang = 2.0 * M_PI * (double)q / (double)m[l];
+      tw.push_back(make_double2(std::cos(ang), -std::sin(ang)));
+    }
+  }
+  hipError_t e = hipMemcpyAsync(c->isoA(), g.data(), sizeof(double2) * ms, hipMemcpyHostToDevice,
+                                c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->tw2(), tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = launch_iso_green(c->isoA(), c->isoB(), c->tw2(), c->tw2_off, m, c->isoG(),
+                                            c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
 }
 
 slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_dev,
@@ -503,6 +578,8 @@ slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_d
       e = hipMemcpyAsync(c->tw(), tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice,
                          c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    c->isolated = (desc->flags & SLMPP_FLAG_ISOLATED) != 0;
+    if (e == hipSuccess && c->isolated) e = iso_setup(c, *desc);
     if (e != hipSuccess) {
       g_error = std::string("upload of field tables: ") + hipGetErrorString(e);
       delete c;

@@ -261,6 +261,63 @@ __global__ void fda_kernel(const double* __restrict__ phi, double* __restrict__ 
   accel[t] = -d;
 }
 
+// ---- isolated boundaries (doubling-up method) -----------------------------
+// the density in the low corner of the doubled grid, zero elsewhere
+__global__ void iso_pad_kernel(const double* __restrict__ rho, double2* __restrict__ out, int3 n,
+                               int3 m, int64_t ms) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ms;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(q % m.z);
+    const int j = (int)((q / m.z) % m.y);
+    const int i = (int)(q / ((int64_t)m.y * m.z));
+    double v = 0.0;
+    if (i < n.x && j < n.y && k < n.z) v = rho[((int64_t)i * n.y + j) * n.z + k];
+    out[q] = make_double2(v, 0.0);
+  }
+}
+
+__global__ void real_part_kernel(const double2* __restrict__ c, double* __restrict__ r, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    r[q] = c[q].x;
+}
+
+// potential of the physical cells and the FDA force from the doubled
+// potential (its values beyond the physical cells are the isolated
+// potential there); pd holds the unnormalised inverse DFT
+__global__ void iso_force_kernel(const double2* __restrict__ pd, int3 n, int3 m, double scale,
+                                 double3 h, int order, double* __restrict__ phi,
+                                 double* __restrict__ accel, int64_t nxs) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nxs;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % n.z);
+    const int j = (int)((t / n.z) % n.y);
+    const int i = (int)(t / ((int64_t)n.y * n.z));
+    const int64_t q = ((int64_t)i * m.y + j) * m.z + k;
+    phi[t] = pd[q].x * scale;
+    const int pos[3] = {i, j, k};
+    const int mm[3] = {m.x, m.y, m.z};
+    const int64_t inner[3] = {(int64_t)m.y * m.z, (int64_t)m.z, 1};
+    const double hh[3] = {h.x, h.y, h.z};
+    for (int l = 0; l < 3; ++l) {
+      const double2* base = pd + (q - (int64_t)pos[l] * inner[l]);
+      auto P = [&](int kk) {
+        int r = (pos[l] + kk) % mm[l];
+        if (r < 0) r += mm[l];
+        return base[(int64_t)r * inner[l]].x * scale;
+      };
+      double d;
+      if (order == 2)
+        d = (P(1) - P(-1)) / (2.0 * hh[l]);
+      else if (order == 4)
+        d = (8.0 * (P(1) - P(-1)) - (P(2) - P(-2))) / (12.0 * hh[l]);
+      else
+        d = (45.0 * (P(1) - P(-1)) - 9.0 * (P(2) - P(-2)) + (P(3) - P(-3))) / (60.0 * hh[l]);
+      accel[(int64_t)l * nxs + t] = -d;
+    }
+  }
+}
+
 // ---- initialisation and conversions -----------------------------------
 template <typename T>
 __global__ void init_separable_kernel(T* __restrict__ f, const double* __restrict__ s,
@@ -454,6 +511,53 @@ hipError_t launch_poisson(const double* rho, double* phi, double* accel, double2
     hipLaunchKernelGGL(fda_kernel, dim3(blocks_for(nxs, NT)), dim3(NT), 0, s, phi,
                        accel + (int64_t)l * nxs, nxs, nx[l], inner, h[l], order);
   }
+  return hipGetLastError();
+}
+
+// Three DFT passes over the doubled grid (sizes m, twiddles per axis at
+// tw + tw_off[l]); returns the buffer holding the result.
+static double2* dft3(double2* a, double2* b, const int64_t* m, const double2* tw,
+                     const int64_t* tw_off, int conj, hipStream_t s) {
+  const int64_t ms = m[0] * m[1] * m[2];
+  constexpr int NT = 256;
+  double2* cur = a;
+  double2* oth = b;
+  for (int l = 0; l < 3; ++l) {
+    int64_t inner = 1;
+    for (int k = l + 1; k < 3; ++k) inner *= m[k];
+    hipLaunchKernelGGL(dft_axis_kernel, dim3(blocks_for(ms, NT)), dim3(NT), 0, s, cur, oth, ms,
+                       m[l], inner, tw + tw_off[l], conj);
+    double2* t = cur;
+    cur = oth;
+    oth = t;
+  }
+  return cur;
+}
+
+hipError_t launch_iso_green(double2* a, double2* b, const double2* tw, const int64_t* tw_off,
+                            const int64_t* m, double* ghat, hipStream_t s) {
+  const int64_t ms = m[0] * m[1] * m[2];
+  double2* res = dft3(a, b, m, tw, tw_off, 0, s);
+  hipLaunchKernelGGL(real_part_kernel, dim3(grid_capped(ms, 256)), dim3(256), 0, s, res, ghat, ms);
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_isolated(const double* rho, double* phi, double* accel, double2* a,
+                                   double2* b, const double2* tw, const int64_t* tw_off,
+                                   const double* ghat, const int64_t* nx, const double* h,
+                                   int order, hipStream_t s) {
+  const int64_t m[3] = {2 * nx[0], 2 * nx[1], 2 * nx[2]};
+  const int64_t ms = m[0] * m[1] * m[2], nxs = nx[0] * nx[1] * nx[2];
+  const int3 n3 = make_int3((int)nx[0], (int)nx[1], (int)nx[2]);
+  const int3 m3 = make_int3((int)m[0], (int)m[1], (int)m[2]);
+  hipLaunchKernelGGL(iso_pad_kernel, dim3(grid_capped(ms, 256)), dim3(256), 0, s, rho, a, n3, m3,
+                     ms);
+  double2* fwd = dft3(a, b, m, tw, tw_off, 0, s);
+  hipLaunchKernelGGL(green_kernel, dim3(blocks_for(ms, 256)), dim3(256), 0, s, fwd, ghat, ms);
+  double2* other = fwd == a ? b : a;
+  double2* inv = dft3(fwd, other, m, tw, tw_off, 1, s);
+  hipLaunchKernelGGL(iso_force_kernel, dim3(grid_capped(nxs, 256)), dim3(256), 0, s, inv, n3, m3,
+                     1.0 / (double)ms, make_double3(h[0], h[1], h[2]), order, phi, accel, nxs);
   return hipGetLastError();
 }
 

@@ -129,6 +129,15 @@ hipError_t launch_poisson(const double* rho, double* phi, double* accel, double2
                           double2* bufB, const double2* twiddles, const int64_t* tw_off,
                           const double* green, int D, const int64_t* nx, const double* h,
                           int order, hipStream_t s);
+// isolated boundaries (D = 3): Fourier transform of the real-space Green
+// function held in a (as complex, doubled grid of sizes m), real part to
+// ghat; the solve itself with a, b as scratch of the doubled size
+hipError_t launch_iso_green(double2* a, double2* b, const double2* tw, const int64_t* tw_off,
+                            const int64_t* m, double* ghat, hipStream_t s);
+hipError_t launch_poisson_isolated(const double* rho, double* phi, double* accel, double2* a,
+                                   double2* b, const double2* tw, const int64_t* tw_off,
+                                   const double* ghat, const int64_t* nx, const double* h,
+                                   int order, hipStream_t s);
 hipError_t launch_init_separable(int dtype, void* f, const double* s, const double* g1,
                                  const double* g2, const double* g3, int D, const int64_t* nv,
                                  int64_t nxs, int64_t nvs, hipStream_t st);

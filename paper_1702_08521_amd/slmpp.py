@@ -22,6 +22,7 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_NONE, LIM_MP, LIM_MPP = 0, 1, 2
 FLAG_RK3 = 1
 FLAG_MERGE_KICKS = 2
+FLAG_ISOLATED = 4
 TIMING_CLASSES = 7
 TIMING_NAMES = ("sweep_strided_w128", "sweep_contiguous", "moment", "poisson",
                 "sweep_strided_other", "pencil_table", "sweep_x1_moment")
@@ -167,7 +168,8 @@ def make_desc(spec, storage=F64) -> GridDesc:
     d.v_bc = int(spec.get("v_bc", BC_OUTFLOW))
     d.storage = int(storage)
     d.flags = (FLAG_RK3 if spec.get("time", "sl") == "rk3" else 0) | \
-        (FLAG_MERGE_KICKS if spec.get("merge_kicks", False) else 0)
+        (FLAG_MERGE_KICKS if spec.get("merge_kicks", False) else 0) | \
+        (FLAG_ISOLATED if spec.get("field_bc", "periodic") == "isolated" else 0)
     return d
 
 

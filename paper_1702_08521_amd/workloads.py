@@ -24,6 +24,8 @@ Workloads (named by what they are):
                   mean density from k/k_J (0.5 or 1.1), SL-MPP5.
   landau_3d3v     electrostatic Landau damping in three dimensions,
                   48^3 x 48^3, x in [0, 4 pi)^3, v in [-6, 6]^3, SL-MPP7.
+  collapse_3d3v   spherical collapse of a uniform-density sphere (Test-4),
+                  64^3 x 32^3, isolated field boundaries, outflow in x, v.
   ensemble        256 independent Landau-type runs of uneven sizes (224
                   1D1V up to 256 x 512, 32 2D2V at 32^2 x 64^2), mixed
                   SL-MPP5/7, seeded k and amplitude.
@@ -154,6 +156,19 @@ def ensemble(n_runs=256, n_2d=32, seed=ENSEMBLE_SEED, nx_1d=(32, 48, 64, 96, 128
     return runs
 
 
+def collapse_3d3v(nx=64, nv=32, order=5, cfl=0.5):
+    """Test-4 of Sec. 3.4: a uniform-density sphere of mass M = 1 and radius
+    2R (R = 1, G = 1, so T = V = 1) with the Maxwellian of sigma^2 = GM/(20R)
+    at every point inside; x, v in [-3, 3]^3, outflow in both, isolated
+    field boundaries."""
+    L, V = 3.0, 3.0
+    s = spec(3, nx, nv, -L, L, -V, V, order=order, kappa=4.0 * math.pi, x_bc=BC_OUTFLOW,
+             v_bc=BC_OUTFLOW, ic="collapse", rho0=3.0 / (32.0 * math.pi), sigma2=0.05,
+             radius=2.0, field_bc="isolated", name="collapse_3d3v")
+    s["dt"] = cfl * spacing(-L, L, nx) / V
+    return s
+
+
 def advection_1d1v(nx, nv, v_lo, v_hi, profile, order=5, limiter=LIM_MPP):
     """Free streaming (no field): every v-row is advected along x with
     speed v; used with a spatial profile of Test-1."""
@@ -195,6 +210,11 @@ def separable_factors(s):
     elif ic == "jeans":
         sx = s["rho_bar"] * (1.0 + s["amp"] * np.cos(s["k"] * grids[0]))
         gv = [maxwellian(v) for v in vs]
+    elif ic == "collapse":
+        r2 = sum(gg * gg for gg in grids)
+        sx = np.where(r2 < s["radius"] ** 2, s["rho0"], 0.0)
+        sig = math.sqrt(s["sigma2"])
+        gv = [maxwellian(v, sig) for v in vs]
     elif ic == "profile":
         sx = test1_profile(s["profile"], grids[0])
         gv = [np.ones_like(v) for v in vs]

@@ -50,7 +50,7 @@ def test_workspace_bytes_positive_for_valid_desc():
     ("poisson_order", 3, slmpp.ERR_INVALID),
     ("storage", 2, slmpp.ERR_INVALID),
     ("x_bc", 5, slmpp.ERR_INVALID),
-    ("flags", 4, slmpp.ERR_INVALID),
+    ("flags", 8, slmpp.ERR_INVALID),
     ("alpha", float("nan"), slmpp.ERR_NONFINITE),
     ("alpha", -1.0, slmpp.ERR_NONFINITE),
 ])
@@ -190,3 +190,15 @@ def test_rk_flag_accepted_and_workspace_grows():
     e = _ensemble()
     e[0].flags = slmpp.FLAG_RK3
     assert slmpp.batch_workspace_bytes(e) == 0
+
+
+def test_isolated_flag_needs_three_dimensions():
+    d = _desc()
+    d.flags = slmpp.FLAG_ISOLATED
+    st, msg = slmpp.validate(d)
+    assert st == slmpp.ERR_INVALID and "D = 3" in msg
+    d3 = slmpp.make_desc(workloads.collapse_3d3v(nx=8, nv=4))
+    assert d3.flags == slmpp.FLAG_ISOLATED
+    assert slmpp.validate(d3)[0] == slmpp.OK
+    plain = slmpp.make_desc(dict(workloads.collapse_3d3v(nx=8, nv=4), field_bc="periodic"))
+    assert slmpp.workspace_bytes(d3) >= slmpp.workspace_bytes(plain) + 40 * 8 * 512

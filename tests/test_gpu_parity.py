@@ -383,3 +383,41 @@ def test_merged_kicks_match_oracle(S, storage):
         err = l1rel(got, ref)
         say(f"  L1 rel = {err:.3e}")
         assert err <= (1e-12 if storage == 0 else 1e-5)
+
+
+def test_isolated_poisson_matches_oracle(S):
+    """Isolated-boundary field solve (doubling-up) on random densities."""
+    import torch
+
+    for nx, order in (((8, 6, 10), 6), ((16, 16, 16), 4), ((5, 7, 4), 2)):
+        spec = W.spec(3, list(nx), [2, 2, 2], [-1.0, -0.6, -1.5], [1.0, 0.9, 1.0], [-1] * 3,
+                      [1] * 3, kappa=4 * np.pi, poisson_order=order, field_bc="isolated",
+                      x_bc=W.BC_OUTFLOW)
+        grid = O.make_grid(spec)
+        say(f"case isolated poisson nx={nx} order={order}")
+        ctx = _ctx(S, spec, 0, np.ones(grid.shape))
+        nxs = int(np.prod(nx))
+        rng = np.random.default_rng(sum(nx))
+        rho = rng.random(nxs)
+        r_t = torch.tensor(rho, dtype=torch.float64, device="cuda")
+        acc = torch.empty(3 * nxs, dtype=torch.float64, device="cuda")
+        phi = torch.empty(nxs, dtype=torch.float64, device="cuda")
+        ctx.poisson_solve(r_t, acc, phi)
+        ctx.sync()
+        ctx.close()
+        phi_o, acc_o = O.poisson_isolated(grid, rho)
+        assert np.abs(phi.cpu().numpy() - phi_o).max() <= 1e-12 * np.abs(phi_o).max()
+        assert np.abs(acc.cpu().numpy() - acc_o).max() <= 1e-12 * np.abs(acc_o).max()
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_collapse_small_matches_oracle(S, storage):
+    """Test-4 physics at 12^3 x 8^3 (isolated field, outflow in x and v),
+    SL-MPP5, 10 steps."""
+    spec = W.collapse_3d3v(nx=12, nv=8, order=5)
+    say(f"case collapse 12^3 x 8^3 storage={storage}")
+    got, ref, diag = _run_pair(S, spec, storage, 10)
+    err = l1rel(got, ref)
+    say(f"  L1 rel = {err:.3e}")
+    assert err <= (1e-12 if storage == 0 else 1e-5)
+    assert diag["nonfinite"] == 0
