@@ -144,8 +144,18 @@ def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ens
     ev1.record(stream)
     ev1.synchronize()
     eager_ms = ev0.elapsed_time(ev1) / steps
+    # the same steps with every sweep in the grouped tile launch (no
+    # persistent launches over runs of one geometry), for comparison
+    b.set_fast_min_cells(-1)
+    b.step(1)
+    ev0.record(stream)
+    b.step(steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    tiles_only_ms = ev0.elapsed_time(ev1) / steps
     log(f"{log_prefix} {len(specs)} runs, {sum(cells):.3e} cells, graph {graph_ms:.3f} ms/step, "
-        f"eager {eager_ms:.3f} ms/step, autotune {tune_s:.2f} s")
+        f"eager {eager_ms:.3f} ms/step, tile launch only {tiles_only_ms:.3f} ms/step, "
+        f"autotune {tune_s:.2f} s")
     out = {
         "runs": len(specs),
         "cells": sum(cells),
@@ -153,6 +163,7 @@ def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ens
         "steps": steps,
         "graph_ms_per_step": round(graph_ms, 4),
         "eager_ms_per_step": round(eager_ms, 4),
+        "tile_launch_only_ms_per_step": round(tiles_only_ms, 4),
         "cell_updates_per_s": updates / (graph_ms * 1e-3),
         "step_GB_s": round(step_bytes / (graph_ms * 1e-3) / 1e9, 1),
         "step_bytes": step_bytes,

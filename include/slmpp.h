@@ -313,7 +313,18 @@ slmpp_status slmpp_batch_get_f(slmpp_batch* b, int32_t run, double* f_host, int6
  * and new choices are appended.  Synchronises. */
 slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path);
 
-/* Tile width chosen for run r's sweep along array axis a (0..2D-1). */
+/* Sweeps of runs with one geometry (the same dims, order, boundaries,
+ * alpha and largest fast shift) that the persistent single-run kernel
+ * takes are advanced by one launch of it per phase when their cells add up
+ * to at least min_cells (default 4194304); the other sweeps stay in the
+ * grouped tile launch.  min_cells < 0: never.  Both forms give the same
+ * results bit for bit.  Rebuilds the launch lists (the step graph is
+ * captured again on the next slmpp_batch_step).  Synchronises. */
+slmpp_status slmpp_batch_set_fast_min_cells(slmpp_batch* b, int64_t min_cells);
+
+/* Tile width chosen for run r's sweep along array axis a (0..2D-1): the
+ * pencils per tile of the launch that advances it (128, 64, 48, 32, 16 or
+ * 8); 0 when the run has no such axis. */
 int32_t slmpp_batch_tile_width(const slmpp_batch* b, int32_t run, int32_t axis);
 
 #ifdef __cplusplus

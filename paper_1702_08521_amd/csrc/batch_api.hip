@@ -69,7 +69,7 @@ constexpr int kMinW = 8;
 
 struct Layout {
   std::vector<size_t> rho, phi, acc, tab;
-  size_t runs, sweeps, items, mitems, scratch, stage, total;
+  size_t runs, sweeps, items, mitems, ptrs, scratch, stage, total;
   int64_t max_sweeps, max_items, nmitems, stage_doubles;
 };
 
@@ -112,6 +112,7 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
   L.sweeps = take(sizeof(BatchSweep) * L.max_sweeps);
   L.items = take(sizeof(BatchItem) * std::max<int64_t>(L.max_items, 1));
   L.mitems = take(sizeof(int2) * std::max<int64_t>(L.nmitems, 1));
+  L.ptrs = take(sizeof(void*) * 2 * L.max_sweeps);  // f and table pointers of fast groups
   L.scratch = take(8 * max_cells);
   L.stage_doubles = std::max<int64_t>(stage, std::min<int64_t>(max_cells, (int64_t)1 << 22));
   L.stage = take(8 * L.stage_doubles);
@@ -152,6 +153,18 @@ std::string shape_key(int dtype, int order, int64_t n, int64_t inner) {
   return o.str();
 }
 
+// Everything the persistent kernel takes from the sweep arguments besides
+// f and the pencil table: sweeps with equal keys can share one launch.
+std::string fast_key(int order, const SweepArgs& a) {
+  std::ostringstream o;
+  o << order << ' ' << a.n << ' ' << a.npen << ' ' << a.inner << ' ' << a.nfast << ' ' << a.bc << ' '
+    << a.cmode << ' ' << a.xdiv << ' ' << a.vdiv << ' ' << a.nvl << ' ' << std::hexfloat << a.alpha;
+  return o.str();
+}
+
+// Default of slmpp_batch_set_fast_min_cells: 16 MiB of FP32 data
+constexpr int64_t kFastMinCells = (int64_t)1 << 22;
+
 }  // namespace
 
 struct slmpp_batch {
@@ -166,10 +179,19 @@ struct slmpp_batch {
   Layout lay{};
   std::vector<SlotDef> slots;
   struct SlotLaunch {
-    int first_sweep, nsweeps, first_item, nitems, max_count, grid;
+    int first_sweep, nsweeps, first_item, nitems, max_count, grid, first_group, ngroups;
     size_t lds;
   };
   std::vector<SlotLaunch> launches;
+  // runs of one geometry advanced by one launch of the persistent kernel
+  struct FastGroup {
+    int order;
+    SweepArgs a;  // fmulti / tmulti / tpr set
+    SweepPlan p;  // tiles over all runs of the group
+  };
+  std::vector<FastGroup> groups;
+  std::vector<void*> group_ptrs;
+  int64_t fast_min_cells = kFastMinCells;
   std::vector<BatchSweep> sweeps;
   std::vector<BatchItem> items;
   std::vector<BatchRun> runs;
@@ -265,14 +287,68 @@ struct slmpp_batch {
     sweeps.clear();
     items.clear();
     launches.clear();
+    groups.clear();
+    group_ptrs.clear();
     run_axis_width.assign((size_t)nruns * 6, 0);
     max_lds = 0;
+    void** dptrs = at<void*>(lay.ptrs);
     for (size_t si = 0; si < slots.size(); ++si) {
-      SlotLaunch L{(int)sweeps.size(), 0, (int)items.size(), 0, 0, 1, 0};
+      SlotLaunch L{(int)sweeps.size(), 0, (int)items.size(), 0, 0, 1, (int)groups.size(), 0, 0};
+      // fast groups: sweeps the persistent kernel takes, of runs with one
+      // geometry, whose cells add up to at least fast_min_cells
+      std::vector<SweepArgs> args((size_t)nruns);
+      std::vector<int64_t> counts((size_t)nruns, 0);
+      std::vector<char> has((size_t)nruns, 0);
+      std::vector<SweepPlan> fplan((size_t)nruns);
+      std::vector<char> grouped((size_t)nruns, 0);
+      std::map<std::string, std::vector<int>> by_key;
       for (int r = 0; r < nruns; ++r) {
-        SweepArgs a;
-        int64_t count = 0;
-        if (!sweep_of(r, slots[si], a, count)) continue;
+        has[r] = sweep_of(r, slots[si], args[r], counts[r]);
+        if (!has[r] || fast_min_cells < 0) continue;
+        const SweepArgs& a = args[r];
+        fplan[r] = plan_sweep(dtype, d[r].order, SLMPP_LIM_MPP, a.n, a.npen, a.inner, a.nfast, 0, 0);
+        if (fplan[r].fast) by_key[fast_key(d[r].order, a)].push_back(r);
+      }
+      for (const auto& kv : by_key) {
+        const std::vector<int>& rs = kv.second;
+        int64_t cells = 0;
+        for (int r : rs) cells += g[r].ncell;
+        if (cells < fast_min_cells) continue;
+        const int r0 = rs[0];
+        FastGroup fg{};
+        fg.order = d[r0].order;
+        fg.a = args[r0];
+        fg.p = fplan[r0];
+        fg.a.tpr = fplan[r0].tiles;
+        fg.p.tiles = fplan[r0].tiles * (int64_t)rs.size();
+        const size_t off = group_ptrs.size();
+        for (int r : rs) group_ptrs.push_back(f[r]);
+        for (int r : rs) group_ptrs.push_back(work + lay.tab[r]);
+        fg.a.fmulti = dptrs + off;
+        fg.a.tmulti = const_cast<const void* const*>(dptrs + off + rs.size());
+        for (int r : rs) grouped[r] = 1;
+        groups.push_back(fg);
+        ++L.ngroups;
+      }
+      for (int r = 0; r < nruns; ++r) {
+        if (!has[r]) continue;
+        const SweepArgs& a = args[r];
+        const int64_t count = counts[r];
+        const int axis = slots[si].vel ? g[r].D + slots[si].l : slots[si].l;
+        if (grouped[r]) {
+          // the table is still computed with the slot's other sweeps
+          run_axis_width[(size_t)r * 6 + axis] = fplan[r].W;
+          BatchSweep b{};
+          b.a = a;
+          b.p = fplan[r];
+          b.table = work + lay.tab[r];
+          b.order = d[r].order;
+          b.count = (int32_t)count;
+          sweeps.push_back(b);
+          L.max_count = std::max<int>(L.max_count, (int)count);
+          ++L.nsweeps;
+          continue;
+        }
         const std::string key = shape_key(dtype, d[r].order, a.n, a.inner);
         // a width from the autotuner or its cache, else (or when it does
         // not fit this shape) the default
@@ -286,7 +362,6 @@ struct slmpp_batch {
         if (!p.lds_bytes)
           return fail(SLMPP_ERR_SHAPE, "run " + std::to_string(r) + ": pencils of " +
                                            std::to_string(a.n) + " cells do not fit a batch tile");
-        const int axis = slots[si].vel ? g[r].D + slots[si].l : slots[si].l;
         run_axis_width[(size_t)r * 6 + axis] = W;
         BatchSweep b{};
         b.a = a;
@@ -305,7 +380,8 @@ struct slmpp_batch {
       max_lds = std::max(max_lds, L.lds);
       launches.push_back(L);
     }
-    if ((int64_t)items.size() > lay.max_items || (int64_t)sweeps.size() > lay.max_sweeps)
+    if ((int64_t)items.size() > lay.max_items || (int64_t)sweeps.size() > lay.max_sweeps ||
+        (int64_t)group_ptrs.size() > 2 * lay.max_sweeps)
       return fail(SLMPP_ERR_WORKSPACE, "batch work lists exceed the workspace");
     hipError_t e = prepare_batch_kernels(dtype, max_lds, max_nxs);
     if (e != hipSuccess) return hip_fail(e, "batch kernel attributes");
@@ -321,6 +397,9 @@ struct slmpp_batch {
                        hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && !items.empty())
       e = hipMemcpyAsync(at<BatchItem>(lay.items), items.data(), sizeof(BatchItem) * items.size(),
+                         hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !group_ptrs.empty())
+      e = hipMemcpyAsync(dptrs, group_ptrs.data(), sizeof(void*) * group_ptrs.size(),
                          hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "upload of batch work lists");
@@ -340,6 +419,10 @@ struct slmpp_batch {
     if (L.nsweeps == 0) return hipSuccess;
     const BatchSweep* sw = at<BatchSweep>(lay.sweeps) + L.first_sweep;
     hipError_t e = launch_batch_tables(dtype, sw, L.nsweeps, L.max_count, s);
+    for (int k = 0; k < L.ngroups && e == hipSuccess; ++k) {
+      const FastGroup& fg = groups[(size_t)(L.first_group + k)];
+      e = launch_sweep(dtype, fg.order, SLMPP_LIM_MPP, fg.a, fg.p, nullptr, s);
+    }
     if (e == hipSuccess)
       e = launch_batch_sweeps(dtype, at<BatchSweep>(lay.sweeps), at<BatchItem>(lay.items) + L.first_item,
                               L.nitems, L.lds, L.grid, s);
@@ -732,6 +815,12 @@ slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     for (const auto& l : fresh) out << l << '\n';
   }
+  return b->build();
+}
+
+slmpp_status slmpp_batch_set_fast_min_cells(slmpp_batch* b, int64_t min_cells) {
+  if (!b) return SLMPP_ERR_INVALID;
+  b->fast_min_cells = min_cells;
   return b->build();
 }
 

@@ -40,6 +40,12 @@ struct SweepArgs {
                         //    number, update with nu = c dt / h, no shift)
   double* mom;          // non-null: per-tile sums of the result over each tile row
                         // (fast strided 64-pencil tiles only), mom[tile * n + i]
+  // several runs of one geometry in one fast launch (batched ensembles):
+  // tile t belongs to run t / tpr, whose f and pencil table are fmulti[r]
+  // and tmulti[r] (null: the single run f, table)
+  void* const* fmulti;
+  const void* const* tmulti;
+  int64_t tpr;
 };
 
 // Tiling of one sweep launch: W pencils per tile, S segments per pencil,

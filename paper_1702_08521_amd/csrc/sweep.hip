@@ -684,21 +684,40 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
     }
   };
 
+  // run and local tile of global tile tt (several runs: see SweepArgs)
+  auto locate = [&](int64_t tt, int64_t& lt) -> int {
+    if (a.fmulti == nullptr) {
+      lt = tt;
+      return 0;
+    }
+    const int r = (int)(tt / a.tpr);
+    lt = tt - (int64_t)r * a.tpr;
+    return r;
+  };
+
   V pf[NV];
   int64_t t = blockIdx.x;
   int wv_next = 0;
-  int64_t gb_next = 0;
+  int64_t gb_next = 0, lt_next = 0;
+  int r_next = 0;
+  T* f_next = f;
   if (t < pl.tiles) {
-    gb_next = tile_base(t, wv_next);
+    r_next = locate(t, lt_next);
+    if (a.fmulti) f_next = reinterpret_cast<T*>(a.fmulti[r_next]);
+    gb_next = tile_base(lt_next, wv_next);
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (vlim[k] < wv_next)
-        pf[k] = __builtin_nontemporal_load(reinterpret_cast<const V*>(f + gb_next + goff0 + k * gstep));
+        pf[k] = __builtin_nontemporal_load(
+            reinterpret_cast<const V*>(f_next + gb_next + goff0 + k * gstep));
   }
   for (; t < pl.tiles; t += gridDim.x) {
     const int wv = wv_next;
     const int64_t gbase = gb_next;
-    const int64_t p0 = t * W;
+    const int64_t p0 = lt_next * W;
+    T* const fc = f_next;
+    const PencilEntry<T>* tabc =
+        a.fmulti ? reinterpret_cast<const PencilEntry<T>*>(a.tmulti[r_next]) : table;
     // ---- pencil entries of this tile ----
     int need_safe = 0;
     if (tid < W) {
@@ -713,7 +732,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
           idx = a.cmode == SPEED_FROM_VELOCITY ? (j / (uint32_t)a.vdiv) % (uint32_t)a.nvl
                                                : o0 / (uint32_t)a.xdiv;
         }
-        const PencilEntry<T>* src = table + idx;
+        const PencilEntry<T>* src = tabc + idx;
         ent[tid] = *src;
         need_safe = src->absN > a.nfast;
       } else {
@@ -755,12 +774,14 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
     }
     // ---- issue the loads of the next tile ----
     if (t + gridDim.x < pl.tiles) {
-      gb_next = tile_base(t + gridDim.x, wv_next);
+      r_next = locate(t + gridDim.x, lt_next);
+      if (a.fmulti) f_next = reinterpret_cast<T*>(a.fmulti[r_next]);
+      gb_next = tile_base(lt_next, wv_next);
 #pragma unroll
       for (int k = 0; k < NV; ++k)
         if (vlim[k] < wv_next)
           pf[k] = __builtin_nontemporal_load(
-              reinterpret_cast<const V*>(f + gb_next + goff0 + k * gstep));
+              reinterpret_cast<const V*>(f_next + gb_next + goff0 + k * gstep));
     }
     // ---- compute ----
     const PencilEntry<T> e = ent[jj];
@@ -792,7 +813,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
       if (vlim[k] < wv) {
         V v;
         get(tile + loff[k], v);
-        __builtin_nontemporal_store(v, reinterpret_cast<V*>(f + gbase + goff0 + k * gstep));
+        __builtin_nontemporal_store(v, reinterpret_cast<V*>(fc + gbase + goff0 + k * gstep));
       }
     }
     if constexpr (MOM) {

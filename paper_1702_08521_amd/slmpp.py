@@ -120,9 +120,14 @@ SIGNATURES = {
     "slmpp_batch_get_f": (_S, [_VP, _I32, _VP, _I64]),
     "slmpp_batch_autotune": (_S, [_VP, ctypes.c_char_p]),
     "slmpp_batch_tile_width": (_I32, [_VP, _I32, _I32]),
+    "slmpp_batch_set_fast_min_cells": (_S, [_VP, ctypes.c_int64]),
 }
 
 _lib = None
+
+
+# SLMPP_ABI_VERSION of include/slmpp.h that these signatures follow
+ABI_VERSION = 2
 
 
 def lib():
@@ -137,6 +142,10 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        v = L.slmpp_abi_version()
+        if v != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {v}, this binding expects "
+                               f"{ABI_VERSION}: rebuild the library")
         _lib = L
     return _lib
 
@@ -421,3 +430,6 @@ class Batch:
 
     def tile_width(self, run, axis):
         return int(lib().slmpp_batch_tile_width(self.h, int(run), int(axis)))
+
+    def set_fast_min_cells(self, min_cells):
+        self._c(lib().slmpp_batch_set_fast_min_cells(self.h, int(min_cells)))

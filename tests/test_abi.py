@@ -25,7 +25,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert slmpp.lib().slmpp_abi_version() == 2
+    m = re.search(r"#define SLMPP_ABI_VERSION (\d+)", open(slmpp.HEADER).read())
+    assert m and int(m.group(1)) == slmpp.ABI_VERSION
+    assert slmpp.lib().slmpp_abi_version() == slmpp.ABI_VERSION
 
 
 def _desc(**kw):

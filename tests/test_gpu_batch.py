@@ -179,6 +179,56 @@ def test_batch_forced_widths_agree(S, tmp_path):
     b.close()
 
 
+def same_geometry_ensemble():
+    """Runs sharing geometries with different k, amplitude and dt, so that
+    the persistent kernel takes several runs per launch; plus a ragged run
+    that stays in the tile launch."""
+    ragged = W.landau_3d3v(n=5, nv=7, order=5, D=3)
+    ragged["nx"] = [5, 4, 6]
+    ragged["nv"] = [7, 6, 8]
+    runs = [W.landau_run(1, 64, 128, k, a, 7) for k, a in ((0.3, 0.01), (0.45, 0.2), (0.6, 0.5))]
+    runs += [W.landau_run(2, 16, 32, k, a, 5) for k, a in ((0.35, 0.05), (0.5, 0.3))]
+    runs.append(W.landau_run(1, 48, 96, 0.4, 0.1, 5))
+    runs.append(ragged)
+    return runs
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_batch_fast_groups_match_oracle_and_tile_launch(S, storage):
+    specs = same_geometry_ensemble()
+    nsteps = 10
+    say(f"case batch fast groups storage={storage} {len(specs)} runs {nsteps} steps")
+    a = _batch(S, specs, storage)
+    a.set_fast_min_cells(1)  # every sweep the persistent kernel takes
+    b = _batch(S, specs, storage)
+    b.set_fast_min_cells(-1)  # none
+    changed = sum(a.tile_width(r, ax) != b.tile_width(r, ax)
+                  for r, s in enumerate(specs) for ax in range(2 * s["D"]))
+    a.step(nsteps)
+    b.step(nsteps)
+    refs = _oracle_runs(specs, storage, nsteps)
+    tol = 1e-12 if storage == 0 else 1e-5
+    for r, (s, ref) in enumerate(zip(specs, refs)):
+        ga, gb = a.get_f(r), b.get_f(r)
+        err = l1rel(ga, ref)
+        say(f"  run {r} {s['name']} D={s['D']} order={s['order']}: L1 rel {err:.3e}")
+        assert np.array_equal(ga, gb), (r, np.abs(ga - gb).max())
+        assert err <= tol, (r, s["name"], err)
+    assert changed > 0
+    # the eager form of the grouped launches, and back to the default
+    a.step_eager(2)
+    b.step(2)
+    for r in range(len(specs)):
+        assert np.array_equal(a.get_f(r), b.get_f(r)), r
+    a.set_fast_min_cells(4 << 20)
+    a.step(1)
+    b.step(1)
+    for r in range(len(specs)):
+        assert np.array_equal(a.get_f(r), b.get_f(r)), r
+    a.close()
+    b.close()
+
+
 def test_batch_error_paths(S):
     specs = ensemble()[:2]
     b = _batch(S, specs, 0)
