@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SLMPP_ABI_VERSION 2
+#define SLMPP_ABI_VERSION 3
 
 typedef enum {
   SLMPP_OK = 0,
@@ -116,6 +116,14 @@ typedef struct {
  * workspace grows by 40 doubles per spatial cell. */
 #define SLMPP_FLAG_ISOLATED 4
 
+/* flags: slmpp_step sweeps every velocity axis of a kick separately.
+ * Without it, when D >= 2, the velocity boundaries are outflow, the limiter
+ * is SLMPP_LIM_MPP, the time integration semi-Lagrangian and the last two
+ * velocity axes have N x N cells with N in {24, 32, 48, 64}, the sweeps
+ * along v_{D-1} and v_D of a kick are done in one pass over f (timing class
+ * 7), with results equal to the separate sweeps bit for bit. */
+#define SLMPP_FLAG_SEPARATE_KICKS 8
+
 typedef struct slmpp_ctx slmpp_ctx;
 
 /* Diagnostics of the current state (Sec. 3: mass, energy, mode amplitude). */
@@ -128,14 +136,16 @@ typedef struct {
 } slmpp_diag_out;
 
 /* Per-kernel-class timing gathered with HIP events on the context stream. */
-#define SLMPP_TIMING_CLASSES 7 /* 0: sweeps along a strided axis, tiles of
+#define SLMPP_TIMING_CLASSES 8 /* 0: sweeps along a strided axis, tiles of
                                      128 pencils,
                                   1: sweeps along the contiguous axis,
                                   2: velocity moment, 3: Poisson + force,
                                   4: sweeps along a strided axis, other tiles,
                                   5: per-pencil shift / weight tables,
                                   6: x_1 sweeps of slmpp_step that also sum
-                                     the velocity moment                 */
+                                     the velocity moment,
+                                  7: the v_{D-1} and v_D sweeps of a kick in
+                                     one pass (two cell updates per cell) */
 typedef struct {
   int64_t launches[SLMPP_TIMING_CLASSES];
   double total_ms[SLMPP_TIMING_CLASSES];  /* summed kernel durations       */

@@ -26,7 +26,7 @@ thread_local std::string g_error;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, stage, mom, rkbuf,
+  size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, table2, stage, mom, rkbuf,
       isoA, isoB, isoG, tw2, total;
   int64_t stage_doubles, mom_doubles;
 };
@@ -68,6 +68,7 @@ Layout layout_of(const slmpp_grid_desc& d) {
   int64_t maxnv = 1;
   for (int l = 0; l < d.D; ++l) maxnv = std::max<int64_t>(maxnv, d.nv[l]);
   L.table = take(pencil_table_bytes(SLMPP_F64, std::max<int64_t>(maxnv, nxs)));
+  L.table2 = take(pencil_table_bytes(SLMPP_F64, nxs));  // second axis of a two-axis kick
   L.stage_doubles = std::max<int64_t>(std::min<int64_t>(kStageChunk, ncell), nxs + sumnv);
   L.stage = take(sizeof(double) * L.stage_doubles);
   // row sums of the x_1 sweep's tiles (fused velocity moment; 64 or 128
@@ -122,8 +123,10 @@ slmpp_status slmpp::check_grid_desc(const slmpp_grid_desc* d, std::string& msg) 
     msg = "x_bc / v_bc must be SLMPP_BC_PERIODIC or SLMPP_BC_OUTFLOW";
     return SLMPP_ERR_INVALID;
   }
-  if ((d->flags & ~(SLMPP_FLAG_RK3 | SLMPP_FLAG_MERGE_KICKS | SLMPP_FLAG_ISOLATED)) != 0) {
-    msg = "flags must combine SLMPP_FLAG_RK3, SLMPP_FLAG_MERGE_KICKS and SLMPP_FLAG_ISOLATED only";
+  if ((d->flags & ~(SLMPP_FLAG_RK3 | SLMPP_FLAG_MERGE_KICKS | SLMPP_FLAG_ISOLATED |
+                    SLMPP_FLAG_SEPARATE_KICKS)) != 0) {
+    msg = "flags must combine SLMPP_FLAG_RK3, SLMPP_FLAG_MERGE_KICKS, SLMPP_FLAG_ISOLATED and "
+          "SLMPP_FLAG_SEPARATE_KICKS only";
     return SLMPP_ERR_INVALID;
   }
   if ((d->flags & SLMPP_FLAG_ISOLATED) && d->D != 3) {
@@ -196,6 +199,7 @@ struct slmpp_ctx {
   double* diagfield() { return reinterpret_cast<double*>(work + lay.diagfield); }
   double* stage() { return reinterpret_cast<double*>(work + lay.stage); }
   void* table() { return work + lay.table; }
+  void* table2() { return work + lay.table2; }
   double* mom() { return reinterpret_cast<double*>(work + lay.mom); }
   double2* isoA() { return reinterpret_cast<double2*>(work + lay.isoA); }
   double2* isoB() { return reinterpret_cast<double2*>(work + lay.isoB); }
@@ -357,6 +361,56 @@ struct slmpp_ctx {
       if (e == hipSuccess) e = toc();
     }
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    return SLMPP_OK;
+  }
+
+  // The two-axis pass of a kick (v_{D-1}, v_D), when its kernel takes this
+  // grid; else lds_bytes == 0.
+  PlanePlan kick_plane_plan() const {
+    if (D < 2 || rk || d.limiter != SLMPP_LIM_MPP || d.v_bc != SLMPP_BC_OUTFLOW ||
+        (d.flags & SLMPP_FLAG_SEPARATE_KICKS))
+      return PlanePlan{};
+    int64_t vouter = 1;
+    for (int l = 0; l < D - 2; ++l) vouter *= d.nv[l];
+    return plan_kick_plane(d.storage, d.order, (int32_t)d.nv[D - 2], (int32_t)d.nv[D - 1],
+                           nxs * vouter, vouter, 4);
+  }
+
+  // The velocity sweeps of one kick, v_1 .. v_D in that order with the
+  // current acceleration; v_{D-1} and v_D in one pass when possible.
+  slmpp_status kick(double dt) {
+    const PlanePlan pp = kick_plane_plan();
+    const int nsep = pp.lds_bytes ? D - 2 : D;
+    slmpp_status st = SLMPP_OK;
+    for (int l = 0; l < nsep && st == SLMPP_OK; ++l) st = sweep(D + l, dt, accel() + (int64_t)l * nxs);
+    if (st != SLMPP_OK || nsep == D) return st;
+    SweepArgs sa[2];
+    for (int k = 0; k < 2; ++k) {
+      const int l = D - 2 + k;
+      SweepArgs& s = sa[k];
+      s = SweepArgs{};
+      s.f = f;
+      s.n = (int32_t)d.nv[l];
+      s.dt = dt;
+      s.alpha = d.alpha;
+      s.cmode = SPEED_FROM_ACCEL;
+      s.accel = accel() + (int64_t)l * nxs;
+      s.xdiv = 1;
+      s.vdiv = 1;
+      s.nvl = 1;
+      s.h = hv[l];
+      s.bc = d.v_bc;
+      s.nfast = 4;
+    }
+    const double cells = (double)ncell;
+    hipError_t e = tic(5, 0.0, 0.0);
+    if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, sa[0], table(), nxs, stream);
+    if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, sa[1], table2(), nxs, stream);
+    if (e == hipSuccess) e = toc();
+    if (e == hipSuccess) e = tic(7, 2.0 * cells * esize(), 2.0 * cells);
+    if (e == hipSuccess) e = launch_kick_plane(d.storage, d.order, sa[0], pp, table(), table2(), stream);
+    if (e == hipSuccess) e = toc();
+    if (e != hipSuccess) return hip_fail(e, "kick launch");
     return SLMPP_OK;
   }
 
@@ -746,16 +800,13 @@ slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
     // v(dt/2) [x block, field, v(dt)]... ending with v(dt/2)
     slmpp_status st = SLMPP_OK;
     if (!c->field_valid) st = c->field();
-    for (int l = 0; l < D && st == SLMPP_OK; ++l)
-      st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
+    if (st == SLMPP_OK) st = c->kick(0.5 * dt);
     for (int32_t it = 0; it < nsteps && st == SLMPP_OK; ++it) {
       bool fused = false;
       for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l)
         st = c->sweep(l, dt, nullptr, l == 0, &fused);
       if (st == SLMPP_OK) st = fused ? c->field_from_rowsums() : c->field();
-      const double kick = it + 1 < nsteps ? dt : 0.5 * dt;
-      for (int l = 0; l < D && st == SLMPP_OK; ++l)
-        st = c->sweep(D + l, kick, c->accel() + (int64_t)l * c->nxs);
+      if (st == SLMPP_OK) st = c->kick(it + 1 < nsteps ? dt : 0.5 * dt);
     }
     if (st != SLMPP_OK) c->field_valid = false;
     return st;
@@ -763,13 +814,11 @@ slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
   for (int32_t it = 0; it < nsteps; ++it) {
     slmpp_status st = SLMPP_OK;
     if (!c->field_valid) st = c->field();
-    for (int l = 0; l < D && st == SLMPP_OK; ++l)
-      st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
+    if (st == SLMPP_OK) st = c->kick(0.5 * dt);
     bool fused = false;
     for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l) st = c->sweep(l, dt, nullptr, l == 0, &fused);
     if (st == SLMPP_OK) st = fused ? c->field_from_rowsums() : c->field();
-    for (int l = 0; l < D && st == SLMPP_OK; ++l)
-      st = c->sweep(D + l, 0.5 * dt, c->accel() + (int64_t)l * c->nxs);
+    if (st == SLMPP_OK) st = c->kick(0.5 * dt);
     if (st != SLMPP_OK) {
       c->field_valid = false;
       return st;

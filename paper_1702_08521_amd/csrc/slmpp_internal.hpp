@@ -69,6 +69,23 @@ hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a,
                         const SweepPlan& p, const void* table, hipStream_t s);
 size_t pencil_table_bytes(int dtype, int64_t count);
 
+// The last two velocity axes of one kick in one pass over f (outflow
+// velocity boundaries, SL-MPP, square planes of N = 24, 32, 48 or 64
+// cells): plane p = (x, v_1..v_{D-2}) is the contiguous block
+// f[p * N^2 .. (p + 1) * N^2); its pencils along v_{D-1} take table entry
+// tabA[p / vouter] and those along v_D tabB[p / vouter].
+struct PlanePlan {
+  int32_t N, PB;       // plane side, planes per tile
+  int32_t G, pitch;    // ghost cells around each plane in LDS, LDS row pitch
+  int32_t plane_lds;   // LDS elements per plane
+  int64_t planes, vouter, tiles;
+  size_t lds_bytes;    // 0: the shape is not supported
+};
+PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t planes,
+                          int64_t vouter, int32_t nfast);
+hipError_t launch_kick_plane(int dtype, int order, const SweepArgs& a, const PlanePlan& p,
+                             const void* tabA, const void* tabB, hipStream_t s);
+
 // Integer-shift bound of a sweep along x_l: max |N| over the velocity
 // centres of axis l, with the same split as the kernels.
 int32_t max_shift_velocity(double vlo, double dv, int32_t nvl, double dt, double h, int32_t n,

@@ -129,6 +129,24 @@ __device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T u_plus, T u_minu
   return th * phib + (T(1) - th) * f0;
 }
 
+// App. A steps 4-7: the bounds f^min, f^max from the curvatures and the
+// median of the flux with them.
+template <typename T>
+__device__ __forceinline__ T mp_clamp(T phi, T fm2, T fm1, T f0, T fp1, T fp2, T alpha) {
+  const T slope = f0 - fm1;
+  const T dm1 = vfma(T(-2), fm1, fm2 + f0);
+  const T d0 = vfma(T(-2), f0, fm1 + fp1);
+  const T dp1 = vfma(T(-2), fp1, f0 + fp2);
+  const T dm4_plus = minmod4(vfma(T(4), d0, -dp1), vfma(T(4), dp1, -d0), d0, dp1);
+  const T dm4_minus = minmod4(vfma(T(4), dm1, -d0), vfma(T(4), d0, -dm1), dm1, d0);
+  const T f_ul = vfma(alpha, slope, f0);
+  const T f_md = vfma(T(-0.5), dm4_plus, T(0.5) * (f0 + fp1));
+  const T f_lc = vfma(T(4.0 / 3.0), dm4_minus, vfma(T(0.5), slope, f0));
+  const T lo = vmax(min3(f0, fp1, f_md), min3(f0, f_ul, f_lc));
+  const T hi = vmin(max3(f0, fp1, f_md), max3(f0, f_ul, f_lc));
+  return med3(phi, lo, hi);
+}
+
 // Interface flux at the face between processing positions m and m+1
 // (upwind cell m).  q holds r_{m-3}..r_{m+3} (seventh order) or
 // r_{m-2}..r_{m+2} (fifth order); the MP constraint works on the five
@@ -144,24 +162,20 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha) {
   } else {
     const T fm2 = q[o], fm1 = q[o + 1], f0 = q[o + 2], fp1 = q[o + 3], fp2 = q[o + 4];
     const T slope = f0 - fm1;
-    // App. A steps 2-3: a value strictly between f_i and f* is accepted
+    // App. A steps 2-3.  The flux is kept when it lies between f_i and f*:
+    // that closed interval always lies within [f^min, f^max] of steps 4-6
+    // (f* is f_i, f_{i+1} <= f^UL or f^UL, each inside both bounds), so
+    // step 7 would return the flux unchanged there.  The strict test of the
+    // text only sends the end points (a flux equal to f_i, as in regions of
+    // zeros) through steps 4-7.
     const T fstar = f0 + minmod2(fp1 - f0, alpha * slope);
-    const bool accept = (phi - f0) * (phi - fstar) < T(0);
+    const bool accept = med3(phi, f0, fstar) == phi;
     T phib = phi;
     // steps 4-7, skipped when every lane of the wavefront accepted (the
-    // common case on smooth data: about half of the VALU work per cell)
+    // common case on smooth data)
     if (!__all(accept)) {
-      const T dm1 = vfma(T(-2), fm1, fm2 + f0);
-      const T d0 = vfma(T(-2), f0, fm1 + fp1);
-      const T dp1 = vfma(T(-2), fp1, f0 + fp2);
-      const T dm4_plus = minmod4(vfma(T(4), d0, -dp1), vfma(T(4), dp1, -d0), d0, dp1);
-      const T dm4_minus = minmod4(vfma(T(4), dm1, -d0), vfma(T(4), d0, -dm1), dm1, d0);
-      const T f_ul = vfma(alpha, slope, f0);
-      const T f_md = vfma(T(-0.5), dm4_plus, T(0.5) * (f0 + fp1));
-      const T f_lc = vfma(T(4.0 / 3.0), dm4_minus, vfma(T(0.5), slope, f0));
-      const T lo = vmax(min3(f0, fp1, f_md), min3(f0, f_ul, f_lc));
-      const T hi = vmin(max3(f0, fp1, f_md), max3(f0, f_ul, f_lc));
-      phib = accept ? phi : med3(phi, lo, hi);
+      const T c = mp_clamp(phi, fm2, fm1, f0, fp1, fp2, alpha);
+      phib = accept ? phi : c;
     }
     if constexpr (LIM == SLMPP_LIM_MPP) {
       // PP limiter, Sec. 2.1.1: keep both half-updates non-negative
@@ -844,6 +858,171 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
   }
 }
 
+// The last two velocity axes of a kick in one pass.  The acceleration
+// depends on x only, so all pencils along v_{D-1} of a plane
+// (x, v_1..v_{D-2}) share one shift and one set of weights, and so do all
+// pencils along v_D; and a plane of N x N cells is one contiguous block of
+// f.  A workgroup stages PB planes at a time in LDS, each inside a ring of
+// G zero cells (outflow), advances the v_{D-1} pencils, writes the results
+// back into the plane, advances the v_D pencils of the updated plane and
+// streams the planes out: the two sweeps one after the other, cell for
+// cell, for one read and one write of f.  Persistent over tiles of PB
+// consecutive planes; the next tile's data and pencil entries are loaded
+// into registers before the current tile is computed (as in
+// sweep_fast_kernel).  One thread per segment of R cells of every pencil
+// of the tile: PB * N * (N / R) threads, PB planes of 4-16 KB (measured:
+// two 48^2 FP32 planes per workgroup of 384 threads took 1.5x as long as
+// one per workgroup of 192).
+template <typename T, int N>
+struct PlaneShape {
+  static constexpr int R = N == 64 ? 16 : (N == 48 ? 12 : 8);  // cells per thread
+  static constexpr int S = N / R;                               // segments per pencil
+  static constexpr int PB = sizeof(T) == 4 ? (N == 24 ? 3 : N == 32 ? 2 : 1) : (N == 24 ? 2 : 1);
+  static constexpr int threads = PB * N * S;
+};
+
+template <typename T, int ORDER, int N>
+__global__ void __launch_bounds__((PlaneShape<T, N>::threads))
+    kick_plane_kernel(SweepArgs a, PlanePlan pl, const PencilEntry<T>* __restrict__ tabA,
+                      const PencilEntry<T>* __restrict__ tabB) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using V = typename Vec<T>::type;
+  using Sh = PlaneShape<T, N>;
+  constexpr int VN = Vec<T>::N;
+  constexpr int R = Sh::R, S = Sh::S, PB = Sh::PB, NT = Sh::threads;
+  constexpr int NN = N * N;
+  constexpr int NVEC = PB * NN / VN;       // 16-byte vectors per tile
+  constexpr int NV = (NVEC + NT - 1) / NT;  // per thread
+  static_assert(N % VN == 0 && N % R == 0 && PB >= 1 && NT <= 1024, "plane shape");
+  const int tid = threadIdx.x;
+  const int G = pl.G, P = pl.pitch, PL = pl.plane_lds;
+  T* lds = reinterpret_cast<T*>(smem);
+  const size_t data_bytes = ((size_t)PB * PL * sizeof(T) + 15) & ~(size_t)15;
+  PencilEntry<T>* ent = reinterpret_cast<PencilEntry<T>*>(smem + data_bytes);
+  T* f = reinterpret_cast<T*>(a.f);
+  const T alpha = (T)a.alpha;
+  // zero the planes with their rings once (interior writes never touch the
+  // rings); the barrier orders these stores before the first tile's data
+  for (int e = tid; e < PB * PL; e += NT) lds[e] = T(0);
+  __syncthreads();
+  // data movement map: vector k of this thread is tile vector tid + NT k,
+  // in plane vq[k] (PB: none) at LDS offset loff[k]
+  int loff[NV], vq[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int v = tid + NT * k;
+    if (v < NVEC) {
+      const int e = v * VN;
+      const int q = e / NN, rem = e - q * NN;
+      const int ia = rem / N, ib = rem - ia * N;
+      loff[k] = q * PL + (ia + G) * P + G + ib;
+      vq[k] = q;
+    } else {
+      loff[k] = 0;
+      vq[k] = PB;
+    }
+  }
+  // compute map: plane cq, pencil cj, cells m0 .. m0 + R - 1
+  const int cq = tid / (N * S);
+  const int cr = tid - cq * (N * S);
+  const int cj = cr % N;
+  const int m0 = (cr / N) * R;
+  const T* colA = lds + cq * PL + G * P + G + cj;    // along v_{D-1}: stride P
+  const T* colB = lds + cq * PL + (G + cj) * P + G;  // along v_D: stride 1
+
+  V pf[NV];
+  // threads < 2 PB: pencil entry of (plane tid / 2, axis tid % 2), as
+  // 16-byte words
+  constexpr int EW = sizeof(PencilEntry<T>) / 16;
+  static_assert(sizeof(PencilEntry<T>) % 16 == 0, "entry size");
+  V en[EW];
+  int np_next = 0;
+  auto issue = [&](int64_t tt) __attribute__((always_inline)) {
+    const int64_t p0 = tt * PB;
+    np_next = (int)min<int64_t>(PB, pl.planes - p0);
+    const V* src = reinterpret_cast<const V*>(f + p0 * NN);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (vq[k] < np_next) pf[k] = __builtin_nontemporal_load(src + tid + NT * k);
+    if (tid < 2 * PB && (tid >> 1) < np_next) {
+      const int64_t ix = udiv(p0 + (tid >> 1), pl.vouter);
+      const V* src = reinterpret_cast<const V*>((tid & 1) ? tabB + ix : tabA + ix);
+#pragma unroll
+      for (int w = 0; w < EW; ++w) en[w] = src[w];
+    }
+  };
+  int64_t t = blockIdx.x;
+  if (t < pl.tiles) issue(t);
+  for (; t < pl.tiles; t += gridDim.x) {
+    const int np = np_next;
+    const int64_t p0 = t * PB;
+    if (tid < 2 * PB) {
+      V* dst = reinterpret_cast<V*>(ent + tid);
+#pragma unroll
+      for (int w = 0; w < EW; ++w) dst[w] = en[w];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (vq[k] < np) put(lds + loff[k], pf[k]);
+    __syncthreads();
+    if (t + gridDim.x < pl.tiles) issue(t + gridDim.x);
+    const bool act = cq < np;
+    T out[R];
+    // v_{D-1}
+    if (act) {
+      const PencilEntry<T> e = ent[2 * cq];
+      if (e.absN <= a.nfast)
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_DIRECT, R>(colA, P, N, G, 0, e, m0, R, alpha, out,
+                                                          nullptr);
+      else
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colA, P, N, G, 0, e, m0, R, alpha, out,
+                                                        nullptr);
+    }
+    __syncthreads();
+    if (act) {
+      const int dir = ent[2 * cq].dir;
+      T* op = const_cast<T*>(colA) + ((dir > 0) ? m0 : (N - 1 - m0)) * P;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        *op = out[k];
+        op += dir * P;
+      }
+    }
+    __syncthreads();
+    // v_D on the updated plane
+    if (act) {
+      const PencilEntry<T> e = ent[2 * cq + 1];
+      if (e.absN <= a.nfast)
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_DIRECT, R>(colB, 1, N, G, 0, e, m0, R, alpha, out,
+                                                          nullptr);
+      else
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colB, 1, N, G, 0, e, m0, R, alpha, out,
+                                                        nullptr);
+    }
+    __syncthreads();
+    if (act) {
+      const int dir = ent[2 * cq + 1].dir;
+      T* op = const_cast<T*>(colB) + ((dir > 0) ? m0 : (N - 1 - m0));
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        *op = out[k];
+        op += dir;
+      }
+    }
+    __syncthreads();
+    V* dst = reinterpret_cast<V*>(f + p0 * NN);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      if (vq[k] < np) {
+        V v;
+        get(lds + loff[k], v);
+        __builtin_nontemporal_store(v, dst + tid + NT * k);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Pencil-table entry for speed index idx (see PencilEntry).
 template <typename T, int ORDER>
 __device__ __forceinline__ PencilEntry<T> pencil_entry(const SweepArgs& a, int idx) {
@@ -1242,6 +1421,83 @@ hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a, c
                       : launch_o<double, 5>(limiter, a, p, table, s);
   return order == 7 ? launch_o<float, 7>(limiter, a, p, table, s)
                     : launch_o<float, 5>(limiter, a, p, table, s);
+}
+
+namespace {
+template <typename T, int ORDER, int N>
+hipError_t launch_plane_t(const SweepArgs& a, const PlanePlan& p, const void* tabA,
+                          const void* tabB, hipStream_t s) {
+  auto kern = kick_plane_kernel<T, ORDER, N>;
+  if (p.lds_bytes > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)p.lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  constexpr int NT = PlaneShape<T, N>::threads;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(kern), NT, p.lds_bytes);
+  if (e != hipSuccess) return e;
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t grid = std::min<int64_t>(p.tiles, (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), p.lds_bytes, s, a, p,
+                     reinterpret_cast<const PencilEntry<T>*>(tabA),
+                     reinterpret_cast<const PencilEntry<T>*>(tabB));
+  return hipGetLastError();
+}
+
+template <typename T, int ORDER>
+hipError_t launch_plane_o(const SweepArgs& a, const PlanePlan& p, const void* tabA,
+                          const void* tabB, hipStream_t s) {
+  switch (p.N) {
+    case 24: return launch_plane_t<T, ORDER, 24>(a, p, tabA, tabB, s);
+    case 32: return launch_plane_t<T, ORDER, 32>(a, p, tabA, tabB, s);
+    case 48: return launch_plane_t<T, ORDER, 48>(a, p, tabA, tabB, s);
+    case 64: return launch_plane_t<T, ORDER, 64>(a, p, tabA, tabB, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t planes,
+                          int64_t vouter, int32_t nfast) {
+  PlanePlan p{};
+  if (na != nb || !(na == 24 || na == 32 || na == 48 || na == 64) || planes < 1 || vouter < 1)
+    return p;
+  const int N = na;
+  p.N = N;
+  if (dtype == SLMPP_F64)
+    p.PB = N == 24 ? 2 : 1;
+  else
+    p.PB = N == 24 ? 3 : (N == 32 ? 2 : 1);  // as PlaneShape
+  p.G = (order == 7 ? 4 : 3) + nfast;
+  p.pitch = (N + 2 * p.G) | 1;  // odd: lanes walking rows hit distinct banks
+  p.plane_lds = (N + 2 * p.G) * p.pitch;
+  p.planes = planes;
+  p.vouter = vouter;
+  p.tiles = (planes + p.PB - 1) / p.PB;
+  const size_t es = dtype == SLMPP_F64 ? 8 : 4;
+  const size_t data = ((size_t)p.PB * p.plane_lds * es + 15) & ~(size_t)15;
+  const size_t lds = data + 2 * (size_t)p.PB * entry_bytes(dtype);
+  p.lds_bytes = lds <= 80 * 1024 ? lds : 0;
+  return p;
+}
+
+hipError_t launch_kick_plane(int dtype, int order, const SweepArgs& a, const PlanePlan& p,
+                             const void* tabA, const void* tabB, hipStream_t s) {
+  if (p.lds_bytes == 0) return hipErrorInvalidValue;
+  if (dtype == SLMPP_F64)
+    return order == 7 ? launch_plane_o<double, 7>(a, p, tabA, tabB, s)
+                      : launch_plane_o<double, 5>(a, p, tabA, tabB, s);
+  return order == 7 ? launch_plane_o<float, 7>(a, p, tabA, tabB, s)
+                    : launch_plane_o<float, 5>(a, p, tabA, tabB, s);
 }
 
 int32_t max_shift_velocity(double vlo, double dv, int32_t nvl, double dt, double h, int32_t n,

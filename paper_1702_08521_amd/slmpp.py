@@ -23,9 +23,10 @@ LIM_NONE, LIM_MP, LIM_MPP = 0, 1, 2
 FLAG_RK3 = 1
 FLAG_MERGE_KICKS = 2
 FLAG_ISOLATED = 4
-TIMING_CLASSES = 7
+FLAG_SEPARATE_KICKS = 8
+TIMING_CLASSES = 8
 TIMING_NAMES = ("sweep_strided_w128", "sweep_contiguous", "moment", "poisson",
-                "sweep_strided_other", "pencil_table", "sweep_x1_moment")
+                "sweep_strided_other", "pencil_table", "sweep_x1_moment", "kick_plane")
 
 
 class SlmppError(RuntimeError):
@@ -127,7 +128,7 @@ _lib = None
 
 
 # SLMPP_ABI_VERSION of include/slmpp.h that these signatures follow
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 def lib():
@@ -178,7 +179,8 @@ def make_desc(spec, storage=F64) -> GridDesc:
     d.storage = int(storage)
     d.flags = (FLAG_RK3 if spec.get("time", "sl") == "rk3" else 0) | \
         (FLAG_MERGE_KICKS if spec.get("merge_kicks", False) else 0) | \
-        (FLAG_ISOLATED if spec.get("field_bc", "periodic") == "isolated" else 0)
+        (FLAG_ISOLATED if spec.get("field_bc", "periodic") == "isolated" else 0) | \
+        (FLAG_SEPARATE_KICKS if spec.get("separate_kicks", False) else 0)
     return d
 
 

@@ -52,7 +52,7 @@ def test_workspace_bytes_positive_for_valid_desc():
     ("poisson_order", 3, slmpp.ERR_INVALID),
     ("storage", 2, slmpp.ERR_INVALID),
     ("x_bc", 5, slmpp.ERR_INVALID),
-    ("flags", 8, slmpp.ERR_INVALID),
+    ("flags", 16, slmpp.ERR_INVALID),
     ("alpha", float("nan"), slmpp.ERR_NONFINITE),
     ("alpha", -1.0, slmpp.ERR_NONFINITE),
 ])
