@@ -373,7 +373,7 @@ struct slmpp_ctx {
     int64_t vouter = 1;
     for (int l = 0; l < D - 2; ++l) vouter *= d.nv[l];
     return plan_kick_plane(d.storage, d.order, (int32_t)d.nv[D - 2], (int32_t)d.nv[D - 1],
-                           nxs * vouter, vouter, 4);
+                           nxs * vouter, vouter);
   }
 
   // The velocity sweeps of one kick, v_1 .. v_D in that order with the

@@ -76,13 +76,15 @@ size_t pencil_table_bytes(int dtype, int64_t count);
 // tabA[p / vouter] and those along v_D tabB[p / vouter].
 struct PlanePlan {
   int32_t N, PB;       // plane side, planes per tile
-  int32_t G, pitch;    // ghost cells around each plane in LDS, LDS row pitch
+  int32_t G, pitch;    // ring of zero cells around each plane in LDS, LDS row
+                       // pitch (fixed by order and N; shifts beyond the ring
+                       // minus the stencil take bounds-checked reads)
   int32_t plane_lds;   // LDS elements per plane
   int64_t planes, vouter, tiles;
   size_t lds_bytes;    // 0: the shape is not supported
 };
 PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t planes,
-                          int64_t vouter, int32_t nfast);
+                          int64_t vouter);
 hipError_t launch_kick_plane(int dtype, int order, const SweepArgs& a, const PlanePlan& p,
                              const void* tabA, const void* tabB, hipStream_t s);
 

@@ -257,6 +257,45 @@ __device__ __forceinline__ void advance(const T* __restrict__ col, int stride, i
   }
 }
 
+// advance() for READ_DIRECT with the stride and the processing direction
+// known at compile time, so that the reads of a segment use fixed offsets
+// from one address.  Same operations, same results.
+template <typename T, int ORDER, int RC, int STRIDE, int DIR>
+__device__ __forceinline__ void advance_ct(const T* __restrict__ col, const PencilEntry<T>& e,
+                                           int m0, T alpha, T* out) {
+  constexpr int H = (ORDER == 7) ? 3 : 2;
+  constexpr int WIN = 2 * H + 1;
+  constexpr int ST = DIR * STRIDE;
+  T w[ORDER];
+#pragma unroll
+  for (int k = 0; k < ORDER; ++k) w[k] = e.w[k];
+  const T z = e.z;
+  const T tz = z + z;
+  const T* ptr = col + (e.base + DIR * (m0 - 1 - H)) * STRIDE;
+  T q[WIN];
+#pragma unroll
+  for (int k = 0; k < WIN; ++k) q[k] = ptr[k * ST];
+  T f_left = face_flux<T, ORDER, SLMPP_LIM_MPP>(q, w, tz, alpha);
+#pragma unroll
+  for (int k = 0; k < RC; ++k) {
+#pragma unroll
+    for (int j = 0; j < WIN - 1; ++j) q[j] = q[j + 1];
+    q[WIN - 1] = ptr[(WIN + k) * ST];
+    const T f_right = face_flux<T, ORDER, SLMPP_LIM_MPP>(q, w, tz, alpha);
+    out[k] = vfma(-z, f_right - f_left, q[H]);
+    f_left = f_right;
+  }
+}
+
+// Store the results of processing positions m0 .. m0 + RC - 1 of a pencil
+// of n cells (physical cells m0 + k, or n - 1 - m0 - k when mirrored).
+template <typename T, int RC, int STRIDE, int DIR>
+__device__ __forceinline__ void store_ct(T* col, int n, int m0, const T* out) {
+  T* op = col + ((DIR > 0) ? m0 : (n - 1 - m0)) * STRIDE;
+#pragma unroll
+  for (int k = 0; k < RC; ++k) op[k * DIR * STRIDE] = out[k];
+}
+
 // 16-byte vectors as native clang vector types (kept in registers)
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
@@ -873,6 +912,8 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
 // of the tile: PB * N * (N / R) threads, PB planes of 4-16 KB (measured:
 // two 48^2 FP32 planes per workgroup of 384 threads took 1.5x as long as
 // one per workgroup of 192).
+constexpr int kPlaneFast = 4;  // integer shifts read directly in the plane kernel
+
 template <typename T, int N>
 struct PlaneShape {
   static constexpr int R = N == 64 ? 16 : (N == 48 ? 12 : 8);  // cells per thread
@@ -895,7 +936,12 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
   constexpr int NV = (NVEC + NT - 1) / NT;  // per thread
   static_assert(N % VN == 0 && N % R == 0 && PB >= 1 && NT <= 1024, "plane shape");
   const int tid = threadIdx.x;
-  const int G = pl.G, P = pl.pitch, PL = pl.plane_lds;
+  // ring width and row pitch are fixed by ORDER and N (shifts up to
+  // kPlaneFast cells read the ring directly); the host plan agrees
+  constexpr int G = (ORDER == 7 ? 4 : 3) + kPlaneFast;
+  constexpr int P = (N + 2 * G) | 1;
+  constexpr int PL = (N + 2 * G) * P;
+  constexpr int SP = P;
   T* lds = reinterpret_cast<T*>(smem);
   const size_t data_bytes = ((size_t)PB * PL * sizeof(T) + 15) & ~(size_t)15;
   PencilEntry<T>* ent = reinterpret_cast<PencilEntry<T>*>(smem + data_bytes);
@@ -971,43 +1017,43 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
     // v_{D-1}
     if (act) {
       const PencilEntry<T> e = ent[2 * cq];
-      if (e.absN <= a.nfast)
-        advance<T, ORDER, SLMPP_LIM_MPP, READ_DIRECT, R>(colA, P, N, G, 0, e, m0, R, alpha, out,
-                                                          nullptr);
-      else
-        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colA, P, N, G, 0, e, m0, R, alpha, out,
+      if (e.absN <= kPlaneFast) {
+        if (e.dir > 0)
+          advance_ct<T, ORDER, R, SP, 1>(colA, e, m0, alpha, out);
+        else
+          advance_ct<T, ORDER, R, SP, -1>(colA, e, m0, alpha, out);
+      } else {
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colA, SP, N, G, 0, e, m0, R, alpha, out,
                                                         nullptr);
+      }
     }
     __syncthreads();
     if (act) {
-      const int dir = ent[2 * cq].dir;
-      T* op = const_cast<T*>(colA) + ((dir > 0) ? m0 : (N - 1 - m0)) * P;
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        *op = out[k];
-        op += dir * P;
-      }
+      if (ent[2 * cq].dir > 0)
+        store_ct<T, R, SP, 1>(const_cast<T*>(colA), N, m0, out);
+      else
+        store_ct<T, R, SP, -1>(const_cast<T*>(colA), N, m0, out);
     }
     __syncthreads();
     // v_D on the updated plane
     if (act) {
       const PencilEntry<T> e = ent[2 * cq + 1];
-      if (e.absN <= a.nfast)
-        advance<T, ORDER, SLMPP_LIM_MPP, READ_DIRECT, R>(colB, 1, N, G, 0, e, m0, R, alpha, out,
-                                                          nullptr);
-      else
+      if (e.absN <= kPlaneFast) {
+        if (e.dir > 0)
+          advance_ct<T, ORDER, R, 1, 1>(colB, e, m0, alpha, out);
+        else
+          advance_ct<T, ORDER, R, 1, -1>(colB, e, m0, alpha, out);
+      } else {
         advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colB, 1, N, G, 0, e, m0, R, alpha, out,
                                                         nullptr);
+      }
     }
     __syncthreads();
     if (act) {
-      const int dir = ent[2 * cq + 1].dir;
-      T* op = const_cast<T*>(colB) + ((dir > 0) ? m0 : (N - 1 - m0));
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        *op = out[k];
-        op += dir;
-      }
+      if (ent[2 * cq + 1].dir > 0)
+        store_ct<T, R, 1, 1>(const_cast<T*>(colB), N, m0, out);
+      else
+        store_ct<T, R, 1, -1>(const_cast<T*>(colB), N, m0, out);
     }
     __syncthreads();
     V* dst = reinterpret_cast<V*>(f + p0 * NN);
@@ -1467,7 +1513,7 @@ hipError_t launch_plane_o(const SweepArgs& a, const PlanePlan& p, const void* ta
 }  // namespace
 
 PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t planes,
-                          int64_t vouter, int32_t nfast) {
+                          int64_t vouter) {
   PlanePlan p{};
   if (na != nb || !(na == 24 || na == 32 || na == 48 || na == 64) || planes < 1 || vouter < 1)
     return p;
@@ -1477,7 +1523,7 @@ PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t 
     p.PB = N == 24 ? 2 : 1;
   else
     p.PB = N == 24 ? 3 : (N == 32 ? 2 : 1);  // as PlaneShape
-  p.G = (order == 7 ? 4 : 3) + nfast;
+  p.G = (order == 7 ? 4 : 3) + kPlaneFast;  // as in kick_plane_kernel
   p.pitch = (N + 2 * p.G) | 1;  // odd: lanes walking rows hit distinct banks
   p.plane_lds = (N + 2 * p.G) * p.pitch;
   p.planes = planes;
