@@ -326,15 +326,25 @@ slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path);
 /* Sweeps of runs with one geometry (the same dims, order, boundaries,
  * alpha and largest fast shift) that the persistent single-run kernel
  * takes are advanced by one launch of it per phase when their cells add up
- * to at least min_cells (default 4194304); the other sweeps stay in the
- * grouped tile launch.  min_cells < 0: never.  Both forms give the same
- * results bit for bit.  Rebuilds the launch lists (the step graph is
- * captured again on the next slmpp_batch_step).  Synchronises. */
+ * to at least min_cells (default 4194304); so are the v_{D-1} and v_D
+ * sweeps of the kicks of runs with one velocity-plane geometry that the
+ * two-axis pass of slmpp_step takes (see SLMPP_FLAG_SEPARATE_KICKS), as
+ * one pass in the v_D phase.  The other sweeps stay in the grouped tile
+ * launch.  min_cells < 0: never.  All forms give the same results bit for
+ * bit.  Rebuilds the launch lists (the step graph is captured again on the
+ * next slmpp_batch_step).  Synchronises. */
 slmpp_status slmpp_batch_set_fast_min_cells(slmpp_batch* b, int64_t min_cells);
+
+/* Algorithmic HBM bytes of one step of the launch lists as built: every
+ * pass over a run's f reads and writes it once (a two-axis kick pass counts
+ * once for its two sweeps) and the velocity moment reads it once.  For
+ * roofline figures; 0 for a NULL batch. */
+double slmpp_batch_step_bytes(const slmpp_batch* b);
 
 /* Tile width chosen for run r's sweep along array axis a (0..2D-1): the
  * pencils per tile of the launch that advances it (128, 64, 48, 32, 16 or
- * 8); 0 when the run has no such axis. */
+ * 8; for the two velocity axes of a two-axis pass, the plane side 24, 32,
+ * 48 or 64); 0 when the run has no such axis. */
 int32_t slmpp_batch_tile_width(const slmpp_batch* b, int32_t run, int32_t axis);
 
 #ifdef __cplusplus

@@ -68,7 +68,7 @@ const int kCandidates[] = {128, 64, 32, 16, 8};
 constexpr int kMinW = 8;
 
 struct Layout {
-  std::vector<size_t> rho, phi, acc, tab;
+  std::vector<size_t> rho, phi, acc, tab, tab2;
   size_t runs, sweeps, items, mitems, ptrs, scratch, stage, total;
   int64_t max_sweeps, max_items, nmitems, stage_doubles;
 };
@@ -98,6 +98,8 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
       sumnv += d[r].nv[l];
     }
     L.tab.push_back(take(pencil_table_bytes(SLMPP_F64, std::max(maxnv, g.nxs))));
+    // v_{D-1} table of a two-axis kick pass
+    L.tab2.push_back(take(g.D >= 2 ? pencil_table_bytes(SLMPP_F64, g.nxs) : 0));
     // work items: every sweep of a step at the smallest tile width
     for (int a = 0; a < 2 * g.D; ++a) {
       const int64_t npen = g.ncell / g.dims[a];
@@ -107,12 +109,13 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
     max_cells = std::max(max_cells, g.ncell);
     stage = std::max(stage, g.nxs + sumnv);
   }
-  L.max_sweeps = (int64_t)n * 3 * Dmax;
+  L.max_sweeps = (int64_t)n * 3 * Dmax + 2 * (int64_t)n;  // plus two v_{D-1} tables per run
   L.runs = take(sizeof(BatchRun) * n);
   L.sweeps = take(sizeof(BatchSweep) * L.max_sweeps);
   L.items = take(sizeof(BatchItem) * std::max<int64_t>(L.max_items, 1));
   L.mitems = take(sizeof(int2) * std::max<int64_t>(L.nmitems, 1));
-  L.ptrs = take(sizeof(void*) * 2 * L.max_sweeps);  // f and table pointers of fast groups
+  // f and table pointers of persistent launches over several runs
+  L.ptrs = take(sizeof(void*) * 4 * L.max_sweeps);
   L.scratch = take(8 * max_cells);
   L.stage_doubles = std::max<int64_t>(stage, std::min<int64_t>(max_cells, (int64_t)1 << 22));
   L.stage = take(8 * L.stage_doubles);
@@ -181,6 +184,7 @@ struct slmpp_batch {
   struct SlotLaunch {
     int first_sweep, nsweeps, first_item, nitems, max_count, grid, first_group, ngroups;
     size_t lds;
+    int first_pgroup, npgroups;
   };
   std::vector<SlotLaunch> launches;
   // runs of one geometry advanced by one launch of the persistent kernel
@@ -190,6 +194,15 @@ struct slmpp_batch {
     SweepPlan p;  // tiles over all runs of the group
   };
   std::vector<FastGroup> groups;
+  // runs of one plane geometry whose v_{D-1} and v_D sweeps of a kick run
+  // as one kick_plane_kernel launch (in the v_D phase)
+  struct PlaneGroup {
+    int order;
+    SweepArgs a;  // alpha, fmulti / tmulti / tpr
+    PlanePlan p;  // tiles over all runs of the group
+  };
+  std::vector<PlaneGroup> pgroups;
+  double step_bytes = 0.0;  // algorithmic HBM bytes of one step as built
   std::vector<void*> group_ptrs;
   int64_t fast_min_cells = kFastMinCells;
   std::vector<BatchSweep> sweeps;
@@ -288,12 +301,52 @@ struct slmpp_batch {
     items.clear();
     launches.clear();
     groups.clear();
+    pgroups.clear();
     group_ptrs.clear();
+    const double es = dtype == SLMPP_F64 ? 8.0 : 4.0;
+    step_bytes = 0.0;
+    for (int r = 0; r < nruns; ++r) step_bytes += es * (double)g[r].ncell;  // the moment
     run_axis_width.assign((size_t)nruns * 6, 0);
     max_lds = 0;
     void** dptrs = at<void*>(lay.ptrs);
+    // two-axis kick passes: runs with one plane geometry (D >= 2, outflow
+    // velocity boundaries, square planes the plane kernel takes) whose
+    // cells add up to at least fast_min_cells
+    std::vector<int> plane_of((size_t)nruns, -1);
+    std::vector<std::vector<int>> pruns;
+    std::vector<PlanePlan> pplan;
+    if (fast_min_cells >= 0) {
+      std::map<std::string, int> pk;
+      for (int r = 0; r < nruns; ++r) {
+        const int D = g[r].D;
+        if (D < 2 || d[r].v_bc != SLMPP_BC_OUTFLOW) continue;
+        int64_t vouter = 1;
+        for (int l = 0; l < D - 2; ++l) vouter *= d[r].nv[l];
+        const PlanePlan pp = plan_kick_plane(dtype, d[r].order, (int32_t)d[r].nv[D - 2],
+                                             (int32_t)d[r].nv[D - 1], g[r].nxs * vouter, vouter);
+        if (!pp.lds_bytes) continue;
+        std::ostringstream o;
+        o << D << ' ' << d[r].order << ' ' << pp.N << ' ' << pp.planes << ' ' << vouter << ' '
+          << std::hexfloat << d[r].alpha;
+        auto it = pk.find(o.str());
+        if (it == pk.end()) {
+          it = pk.emplace(o.str(), (int)pruns.size()).first;
+          pruns.emplace_back();
+          pplan.push_back(pp);
+        }
+        pruns[(size_t)it->second].push_back(r);
+      }
+      for (size_t q = 0; q < pruns.size(); ++q) {
+        int64_t cells = 0;
+        for (int r : pruns[q]) cells += g[r].ncell;
+        if (cells >= fast_min_cells)
+          for (int r : pruns[q]) plane_of[r] = (int)q;
+      }
+    }
     for (size_t si = 0; si < slots.size(); ++si) {
-      SlotLaunch L{(int)sweeps.size(), 0, (int)items.size(), 0, 0, 1, (int)groups.size(), 0, 0};
+      SlotLaunch L{(int)sweeps.size(), 0, (int)items.size(), 0, 0, 1, (int)groups.size(), 0, 0,
+                   (int)pgroups.size(), 0};
+      std::vector<int> pg_here;  // plane groups launched in this phase
       // fast groups: sweeps the persistent kernel takes, of runs with one
       // geometry, whose cells add up to at least fast_min_cells
       std::vector<SweepArgs> args((size_t)nruns);
@@ -304,6 +357,34 @@ struct slmpp_batch {
       std::map<std::string, std::vector<int>> by_key;
       for (int r = 0; r < nruns; ++r) {
         has[r] = sweep_of(r, slots[si], args[r], counts[r]);
+        if (has[r] && plane_of[r] >= 0 && slots[si].vel && slots[si].l >= g[r].D - 2) {
+          // v_{D-1}: done with v_D; v_D: the two tables now, the pass below
+          has[r] = 0;
+          if (slots[si].l == g[r].D - 1) {
+            const int q = plane_of[r];
+            if (std::find(pg_here.begin(), pg_here.end(), q) == pg_here.end()) pg_here.push_back(q);
+            SlotDef sa = slots[si];
+            sa.l = g[r].D - 2;
+            BatchSweep ta{}, tb{};
+            int64_t ca = 0;
+            sweep_of(r, sa, ta.a, ca);
+            ta.table = work + lay.tab2[r];
+            ta.order = d[r].order;
+            ta.count = (int32_t)ca;
+            tb.a = args[r];
+            tb.table = work + lay.tab[r];
+            tb.order = d[r].order;
+            tb.count = (int32_t)counts[r];
+            sweeps.push_back(ta);
+            sweeps.push_back(tb);
+            L.nsweeps += 2;
+            L.max_count = std::max<int>(L.max_count, (int)std::max(ca, counts[r]));
+            run_axis_width[(size_t)r * 6 + 2 * g[r].D - 2] = pplan[(size_t)q].N;
+            run_axis_width[(size_t)r * 6 + 2 * g[r].D - 1] = pplan[(size_t)q].N;
+          }
+          continue;
+        }
+        if (has[r]) step_bytes += 2.0 * es * (double)g[r].ncell;
         if (!has[r] || fast_min_cells < 0) continue;
         const SweepArgs& a = args[r];
         fplan[r] = plan_sweep(dtype, d[r].order, SLMPP_LIM_MPP, a.n, a.npen, a.inner, a.nfast, 0, 0);
@@ -376,12 +457,32 @@ struct slmpp_batch {
         L.lds = std::max(L.lds, p.lds_bytes);
         ++L.nsweeps;
       }
+      for (int q : pg_here) {
+        const std::vector<int>& rs = pruns[(size_t)q];
+        const int r0 = rs[0];
+        PlaneGroup pg{};
+        pg.order = d[r0].order;
+        pg.a.alpha = d[r0].alpha;
+        pg.a.nfast = 4;
+        pg.p = pplan[(size_t)q];
+        pg.a.tpr = pg.p.tiles;
+        pg.p.tiles *= (int64_t)rs.size();
+        const size_t off = group_ptrs.size();
+        for (int r : rs) group_ptrs.push_back(f[r]);
+        for (int r : rs) step_bytes += 2.0 * es * (double)g[r].ncell;
+        for (int r : rs) group_ptrs.push_back(work + lay.tab2[r]);
+        for (int r : rs) group_ptrs.push_back(work + lay.tab[r]);
+        pg.a.fmulti = dptrs + off;
+        pg.a.tmulti = const_cast<const void* const*>(dptrs + off + rs.size());
+        pgroups.push_back(pg);
+        ++L.npgroups;
+      }
       L.nitems = (int)items.size() - L.first_item;
       max_lds = std::max(max_lds, L.lds);
       launches.push_back(L);
     }
     if ((int64_t)items.size() > lay.max_items || (int64_t)sweeps.size() > lay.max_sweeps ||
-        (int64_t)group_ptrs.size() > 2 * lay.max_sweeps)
+        (int64_t)group_ptrs.size() > 4 * lay.max_sweeps)
       return fail(SLMPP_ERR_WORKSPACE, "batch work lists exceed the workspace");
     hipError_t e = prepare_batch_kernels(dtype, max_lds, max_nxs);
     if (e != hipSuccess) return hip_fail(e, "batch kernel attributes");
@@ -422,6 +523,10 @@ struct slmpp_batch {
     for (int k = 0; k < L.ngroups && e == hipSuccess; ++k) {
       const FastGroup& fg = groups[(size_t)(L.first_group + k)];
       e = launch_sweep(dtype, fg.order, SLMPP_LIM_MPP, fg.a, fg.p, nullptr, s);
+    }
+    for (int k = 0; k < L.npgroups && e == hipSuccess; ++k) {
+      const PlaneGroup& pg = pgroups[(size_t)(L.first_pgroup + k)];
+      e = launch_kick_plane(dtype, pg.order, pg.a, pg.p, nullptr, nullptr, s);
     }
     if (e == hipSuccess)
       e = launch_batch_sweeps(dtype, at<BatchSweep>(lay.sweeps), at<BatchItem>(lay.items) + L.first_item,
@@ -823,6 +928,8 @@ slmpp_status slmpp_batch_set_fast_min_cells(slmpp_batch* b, int64_t min_cells) {
   b->fast_min_cells = min_cells;
   return b->build();
 }
+
+double slmpp_batch_step_bytes(const slmpp_batch* b) { return b ? b->step_bytes : 0.0; }
 
 int32_t slmpp_batch_tile_width(const slmpp_batch* b, int32_t run, int32_t axis) {
   if (!b || run < 0 || run >= b->nruns || axis < 0 || axis >= 2 * b->g[run].D) return 0;

@@ -73,7 +73,11 @@ size_t pencil_table_bytes(int dtype, int64_t count);
 // velocity boundaries, SL-MPP, square planes of N = 24, 32, 48 or 64
 // cells): plane p = (x, v_1..v_{D-2}) is the contiguous block
 // f[p * N^2 .. (p + 1) * N^2); its pencils along v_{D-1} take table entry
-// tabA[p / vouter] and those along v_D tabB[p / vouter].
+// tabA[p / vouter] and those along v_D tabB[p / vouter].  Several runs of
+// one geometry in one launch: SweepArgs::fmulti / tmulti / tpr (tiles per
+// run) with tmulti holding the v_{D-1} tables of the runs, then their v_D
+// tables; planes and tiles as for one run, times the number of runs for
+// tiles.
 struct PlanePlan {
   int32_t N, PB;       // plane side, planes per tile
   int32_t G, pitch;    // ring of zero cells around each plane in LDS, LDS row

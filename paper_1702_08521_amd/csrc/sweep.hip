@@ -982,17 +982,33 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
   constexpr int EW = sizeof(PencilEntry<T>) / 16;
   static_assert(sizeof(PencilEntry<T>) % 16 == 0, "entry size");
   V en[EW];
+  // several runs of one geometry (batched ensembles): tile tt belongs to
+  // run tt / tpr with f fmulti[r] and tables tmulti[r] (v_{D-1}) and
+  // tmulti[nrun + r] (v_D); pl.planes counts the planes of one run
+  const int64_t nrun = a.fmulti ? pl.tiles / a.tpr : 1;
   int np_next = 0;
+  int64_t p0_next = 0;
+  T* f_next = f;
   auto issue = [&](int64_t tt) __attribute__((always_inline)) {
-    const int64_t p0 = tt * PB;
-    np_next = (int)min<int64_t>(PB, pl.planes - p0);
-    const V* src = reinterpret_cast<const V*>(f + p0 * NN);
+    int64_t lt = tt;
+    const PencilEntry<T>* ta = tabA;
+    const PencilEntry<T>* tb = tabB;
+    if (a.fmulti) {
+      const int64_t r = tt / a.tpr;
+      lt = tt - r * a.tpr;
+      f_next = reinterpret_cast<T*>(a.fmulti[r]);
+      ta = reinterpret_cast<const PencilEntry<T>*>(a.tmulti[r]);
+      tb = reinterpret_cast<const PencilEntry<T>*>(a.tmulti[nrun + r]);
+    }
+    p0_next = lt * PB;
+    np_next = (int)min<int64_t>(PB, pl.planes - p0_next);
+    const V* src = reinterpret_cast<const V*>(f_next + p0_next * NN);
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (vq[k] < np_next) pf[k] = __builtin_nontemporal_load(src + tid + NT * k);
     if (tid < 2 * PB && (tid >> 1) < np_next) {
-      const int64_t ix = udiv(p0 + (tid >> 1), pl.vouter);
-      const V* src = reinterpret_cast<const V*>((tid & 1) ? tabB + ix : tabA + ix);
+      const int64_t ix = udiv(p0_next + (tid >> 1), pl.vouter);
+      const V* src = reinterpret_cast<const V*>((tid & 1) ? tb + ix : ta + ix);
 #pragma unroll
       for (int w = 0; w < EW; ++w) en[w] = src[w];
     }
@@ -1001,7 +1017,8 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
   if (t < pl.tiles) issue(t);
   for (; t < pl.tiles; t += gridDim.x) {
     const int np = np_next;
-    const int64_t p0 = t * PB;
+    const int64_t p0 = p0_next;
+    T* const fc = f_next;
     if (tid < 2 * PB) {
       V* dst = reinterpret_cast<V*>(ent + tid);
 #pragma unroll
@@ -1056,7 +1073,7 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
         store_ct<T, R, 1, -1>(const_cast<T*>(colB), N, m0, out);
     }
     __syncthreads();
-    V* dst = reinterpret_cast<V*>(f + p0 * NN);
+    V* dst = reinterpret_cast<V*>(fc + p0 * NN);
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       if (vq[k] < np) {

@@ -122,6 +122,7 @@ SIGNATURES = {
     "slmpp_batch_autotune": (_S, [_VP, ctypes.c_char_p]),
     "slmpp_batch_tile_width": (_I32, [_VP, _I32, _I32]),
     "slmpp_batch_set_fast_min_cells": (_S, [_VP, ctypes.c_int64]),
+    "slmpp_batch_step_bytes": (ctypes.c_double, [_VP]),
 }
 
 _lib = None
@@ -435,3 +436,6 @@ class Batch:
 
     def set_fast_min_cells(self, min_cells):
         self._c(lib().slmpp_batch_set_fast_min_cells(self.h, int(min_cells)))
+
+    def step_bytes(self):
+        return float(lib().slmpp_batch_step_bytes(self.h))

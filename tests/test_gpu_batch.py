@@ -181,8 +181,8 @@ def test_batch_forced_widths_agree(S, tmp_path):
 
 def same_geometry_ensemble():
     """Runs sharing geometries with different k, amplitude and dt, so that
-    the persistent kernel takes several runs per launch; plus a ragged run
-    that stays in the tile launch."""
+    the persistent kernels take several runs per launch (sweeps and the
+    two-axis kick pass); plus a ragged run that stays in the tile launch."""
     ragged = W.landau_3d3v(n=5, nv=7, order=5, D=3)
     ragged["nx"] = [5, 4, 6]
     ragged["nv"] = [7, 6, 8]
@@ -190,6 +190,7 @@ def same_geometry_ensemble():
     runs += [W.landau_run(2, 16, 32, k, a, 5) for k, a in ((0.35, 0.05), (0.5, 0.3))]
     runs.append(W.landau_run(1, 48, 96, 0.4, 0.1, 5))
     runs.append(ragged)
+    runs.append(W.landau_run(3, 4, 24, 0.45, 0.1, 7))  # 24^2 velocity planes, v1 separate
     return runs
 
 
@@ -204,6 +205,11 @@ def test_batch_fast_groups_match_oracle_and_tile_launch(S, storage):
     b.set_fast_min_cells(-1)  # none
     changed = sum(a.tile_width(r, ax) != b.tile_width(r, ax)
                   for r, s in enumerate(specs) for ax in range(2 * s["D"]))
+    # the last two velocity axes of the 2D2V and 3D3V runs: the two-axis pass
+    for r, s in enumerate(specs):
+        if s["D"] >= 2 and s["nv"][s["D"] - 2] == s["nv"][s["D"] - 1] in (24, 32, 48, 64):
+            D = s["D"]
+            assert a.tile_width(r, 2 * D - 2) == a.tile_width(r, 2 * D - 1) == s["nv"][D - 1], r
     a.step(nsteps)
     b.step(nsteps)
     refs = _oracle_runs(specs, storage, nsteps)
