@@ -203,6 +203,13 @@ slmpp_status slmpp_advect_x(slmpp_ctx* ctx, int32_t dim, double dt);
  * the device), Eq. (adv_vel).  In place. */
 slmpp_status slmpp_advect_v(slmpp_ctx* ctx, int32_t dim, double dt, const double* accel_dev);
 
+/* One velocity kick: SL steps along v_1, .., v_D in that order, each by dt
+ * with the context's acceleration (computed from f first when f changed
+ * since the last field solve), as in the half-kicks of slmpp_step: the last
+ * two axes in one pass when the two-axis kernel takes the grid (see
+ * SLMPP_FLAG_SEPARATE_KICKS).  Leaves the field stale.  In place. */
+slmpp_status slmpp_kick(slmpp_ctx* ctx, double dt);
+
 /* rho_dev[ix] <- dv^D * sum_v f(ix, v) (compensated double accumulation). */
 slmpp_status slmpp_density_moment(slmpp_ctx* ctx, double* rho_dev);
 

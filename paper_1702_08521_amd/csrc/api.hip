@@ -722,6 +722,16 @@ slmpp_status slmpp_advect_v(slmpp_ctx* c, int32_t dim, double dt, const double* 
   return c->sweep(c->D + dim, dt, accel_dev);
 }
 
+slmpp_status slmpp_kick(slmpp_ctx* c, double dt) {
+  if (!c) return SLMPP_ERR_INVALID;
+  if (!std::isfinite(dt)) return c->fail(SLMPP_ERR_NONFINITE, "dt is not finite");
+  slmpp_status st = SLMPP_OK;
+  if (!c->field_valid) st = c->field();
+  if (st != SLMPP_OK || dt == 0.0) return st;
+  c->field_valid = false;
+  return c->kick(dt);
+}
+
 slmpp_status slmpp_density_moment(slmpp_ctx* c, double* rho_dev) {
   if (!c) return SLMPP_ERR_INVALID;
   if (!rho_dev) return c->fail(SLMPP_ERR_INVALID, "rho_dev is NULL");

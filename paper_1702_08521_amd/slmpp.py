@@ -95,6 +95,7 @@ SIGNATURES = {
     "slmpp_init_f_separable": (_S, [_VP, _VP, _VP, _VP, _VP]),
     "slmpp_advect_x": (_S, [_VP, _I32, _D]),
     "slmpp_advect_v": (_S, [_VP, _I32, _D, _VP]),
+    "slmpp_kick": (_S, [_VP, ctypes.c_double]),
     "slmpp_density_moment": (_S, [_VP, _VP]),
     "slmpp_poisson_solve": (_S, [_VP, _VP, _VP, _VP]),
     "slmpp_velocity_moments": (_S, [_VP, _VP, _VP, _VP]),
@@ -276,6 +277,10 @@ class Context:
     def advect_v(self, dim, dt, accel):
         """accel: CUDA float64 tensor of prod(nx) values (this component)."""
         self._c(lib().slmpp_advect_v(self.h, int(dim), float(dt), _VP(accel.data_ptr())))
+
+    def kick(self, dt):
+        """All velocity axes by dt with the context's acceleration."""
+        self._c(lib().slmpp_kick(self.h, float(dt)))
 
     def density_moment(self, rho):
         self._c(lib().slmpp_density_moment(self.h, _VP(rho.data_ptr())))

@@ -126,3 +126,47 @@ def test_fullsize_jeans_independent_of_x2_x3(S):
         rel = (torch.abs(col - ref).max() / torch.abs(ref).max()).item()
         assert rel <= 1e-6, (i2, i3, rel)
     ctx.close()
+
+
+@pytest.mark.parametrize("which", ["landau_3d3v_48", "jeans_3d3v_32"])
+def test_fullsize_kick_velocity_blocks(S, which):
+    """A velocity kick at the benchmark size (v1 sweep, then the two-axis
+    pass over the (v2, v3) planes), checked on the whole velocity block of
+    sampled spatial cells: the kick acts on each block alone with that
+    cell's acceleration.  The oracle rounds to FP32 after each sweep, as the
+    GPU stores between sweeps (in HBM after v1, in LDS after v2)."""
+    spec = W.landau_3d3v(n=48, order=7) if which == "landau_3d3v_48" else W.jeans_3d3v(n=32, order=5)
+    D = spec["D"]
+    ctx = S.Context(S.make_desc(spec, S.F32))
+    s, gv = W.separable_factors(spec)
+    ctx.init_f_separable(s, gv)
+    ctx.field()
+    _, acc = ctx.get_field()
+    f = ctx.f
+    shape = tuple(f.shape)
+    nxs = int(np.prod(shape[:D]))
+    rng = np.random.default_rng(11)
+    cells = [tuple(int(rng.integers(0, n)) for n in shape[:D]) for _ in range(6)]
+    before = [f[c].double().cpu().numpy() for c in cells]
+    dt = 0.5 * spec["dt"]
+    ctx.timing_enable(True)
+    ctx.kick(dt)
+    tim = ctx.timing_read()
+    assert tim["kick_plane"]["launches"] == 1
+    say(f"case {which} kick on {len(cells)} velocity blocks")
+    worst = 0.0
+    for c, blk in zip(cells, before):
+        ix = int(np.ravel_multi_index(c, shape[:D]))
+        ref = blk.copy()
+        for l in range(D):
+            h = (spec["v_hi"][l] - spec["v_lo"][l]) / spec["nv"][l]
+            xi = O.xi(acc[l * nxs + ix], dt, h)
+            O.sweep_lines(ref, l, xi, order=spec["order"], limiter=spec["limiter"],
+                          alpha=spec["alpha"], bc=spec["v_bc"])
+            ref = ref.astype(np.float32).astype(np.float64)
+        got = f[c].double().cpu().numpy()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+        assert err <= 64 * 2.0 ** -24, (c, err)
+    say(f"  worst block error {worst:.3e} (FP32 ulps of max: {worst / 2.0 ** -24:.1f})")
+    ctx.close()
