@@ -109,18 +109,33 @@ __device__ void lds_dft(const double2* in, double2* out, const double2* tw, int 
     const int k = (t / inner) % n;
     const int o = t / (inner * n);
     const double2* src = in + o * n * inner + j;
-    double sr = 0.0, si = 0.0;
+    // four interleaved partial sums (m mod 4): independent chains of LDS
+    // reads and multiply-adds, added in a fixed order at the end
+    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
     int q = 0;
-    for (int m = 0; m < n; ++m) {
+    int m = 0;
+    for (; m + 3 < n; m += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double cs = tw[q].x;
+        const double sn = sign * tw[q].y;
+        const double2 x = src[(m + u) * inner];
+        sr[u] += x.x * cs - x.y * sn;
+        si[u] += x.x * sn + x.y * cs;
+        q += k;
+        if (q >= n) q -= n;
+      }
+    }
+    for (; m < n; ++m) {
       const double cs = tw[q].x;
       const double sn = sign * tw[q].y;
       const double2 x = src[m * inner];
-      sr += x.x * cs - x.y * sn;
-      si += x.x * sn + x.y * cs;
+      sr[0] += x.x * cs - x.y * sn;
+      si[0] += x.x * sn + x.y * cs;
       q += k;
       if (q >= n) q -= n;
     }
-    out[t] = make_double2(sr, si);
+    out[t] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
   }
 }
 

@@ -528,6 +528,9 @@ struct slmpp_batch {
       const PlaneGroup& pg = pgroups[(size_t)(L.first_pgroup + k)];
       e = launch_kick_plane(dtype, pg.order, pg.a, pg.p, nullptr, nullptr, s);
     }
+    // (the tile launch after the group launches: run beside them on a
+    // second stream it took CU slots from the persistent kernels and made
+    // the phase slower)
     if (e == hipSuccess)
       e = launch_batch_sweeps(dtype, at<BatchSweep>(lay.sweeps), at<BatchItem>(lay.items) + L.first_item,
                               L.nitems, L.lds, L.grid, s);
