@@ -23,6 +23,11 @@
 //    by both neighbouring cells; each thread owns a segment of R cells),
 //    writes the results back into the LDS tile and streams it out in place.
 //    A sweep therefore reads and writes f exactly once; halos stay on chip.
+//    sweep_fast_kernel is its persistent form with the next tile prefetched
+//    into registers (several runs of one geometry per launch for batched
+//    ensembles); batch_sweep_kernel walks a list of tiles of many runs.
+//  * kick_plane_kernel: the sweeps along the last two velocity axes of a
+//    kick in one pass over f, whole velocity planes in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

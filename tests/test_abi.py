@@ -94,6 +94,9 @@ def test_null_context_is_rejected():
     L = slmpp.lib()
     assert L.slmpp_advect_x(None, 0, 0.1) == slmpp.ERR_INVALID
     assert L.slmpp_step(None, 0.1, 1) == slmpp.ERR_INVALID
+    assert L.slmpp_kick(None, 0.1) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_set_fast_min_cells(None, 0) == slmpp.ERR_INVALID
+    assert L.slmpp_batch_step_bytes(None) == 0.0
     assert L.slmpp_destroy(None) == slmpp.ERR_INVALID
 
 
