@@ -348,16 +348,24 @@ struct slmpp_ctx {
       if (e == hipSuccess) e = toc();
     } else {
       // Eq. (RK): f1 = S(f), f2 = 3/4 f + 1/4 S(f1), f^{n+1} = 1/3 f + 2/3 S(f2),
-      // S(u) = u - nu L(u) one stage sweep in place; f^n is kept in rkbuf
-      const size_t bytes = (size_t)ncell * esize();
-      if (e == hipSuccess) e = tic(cls, 14.0 * cells * esize(), 3.0 * cells);
-      if (e == hipSuccess) e = hipMemcpyAsync(rkbuf(), f, bytes, hipMemcpyDeviceToDevice, stream);
-      const double cb[3] = {0.0, 0.75, 1.0 / 3.0}, cf[3] = {1.0, 0.25, 2.0 / 3.0};
-      for (int st = 0; st < 3 && e == hipSuccess; ++st) {
-        e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);
-        if (e == hipSuccess && st > 0)
-          e = launch_blend(d.storage, f, rkbuf(), cb[st], cf[st], ncell, stream);
-      }
+      // S(u) = u - nu L(u) one stage sweep.  The stages run out of place
+      // with the combinations in their stores, f^n staying in f: f1 and f2
+      // in rkbuf, the last stage back into f (8 passes over f per sweep)
+      if (e == hipSuccess) e = tic(cls, 8.0 * cells * esize(), 3.0 * cells);
+      SweepArgs s1 = s, s2 = s, s3 = s;
+      s1.fout = rkbuf();
+      s2.f = rkbuf();
+      s2.fblend = f;
+      s2.cb = 0.75;
+      s2.cf = 0.25;
+      s3.f = rkbuf();
+      s3.fout = f;
+      s3.fblend = f;
+      s3.cb = 1.0 / 3.0;
+      s3.cf = 2.0 / 3.0;
+      if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s1, p, table(), stream);
+      if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s2, p, table(), stream);
+      if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s3, p, table(), stream);
       if (e == hipSuccess) e = toc();
     }
     if (e != hipSuccess) return hip_fail(e, "sweep launch");

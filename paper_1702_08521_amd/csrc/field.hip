@@ -434,15 +434,6 @@ __global__ void __launch_bounds__(NT) diag_field_kernel(const double* __restrict
 }
 
 // f <- cb * b + cf * f (the stage combinations of Eq. (RK)), grid-stride
-template <typename T>
-__global__ void __launch_bounds__(256) blend_kernel(T* __restrict__ f, const T* __restrict__ b,
-                                                    double cb, double cf, int64_t n) {
-  const T tb = (T)cb, tf = (T)cf;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    f[i] = tb * b[i] + tf * f[i];
-}
-
 __global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -660,20 +651,6 @@ hipError_t launch_velocity_distribution(int dtype, const void* f, int64_t nxs, i
   else
     hipLaunchKernelGGL(velocity_distribution_kernel<float>, dim3((unsigned)blocks), dim3(256), 0,
                        s, (const float*)f, nxs, nvs, xvol, F);
-  return hipGetLastError();
-}
-
-hipError_t launch_blend(int dtype, void* f, const void* b, double cb, double cf, int64_t n,
-                        hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  constexpr int NT = 256;
-  const int64_t blocks = std::min<int64_t>((n + NT - 1) / NT, 256 * 64);
-  if (dtype == SLMPP_F64)
-    hipLaunchKernelGGL(blend_kernel<double>, dim3((unsigned)blocks), dim3(NT), 0, s, (double*)f,
-                       (const double*)b, cb, cf, n);
-  else
-    hipLaunchKernelGGL(blend_kernel<float>, dim3((unsigned)blocks), dim3(NT), 0, s, (float*)f,
-                       (const float*)b, cb, cf, n);
   return hipGetLastError();
 }
 

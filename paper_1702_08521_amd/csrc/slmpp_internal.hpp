@@ -46,6 +46,13 @@ struct SweepArgs {
   void* const* fmulti;
   const void* const* tmulti;
   int64_t tpr;
+  // stages of the TVD-RK time integration (single runs, sweep_fast_kernel
+  // and the tile kernels): the results go to fout (null: f, in place),
+  // and with fblend non-null each result r becomes cb * fblend + cf * r at
+  // the same element
+  void* fout;
+  const void* fblend;
+  double cb, cf;
 };
 
 // Tiling of one sweep launch: W pencils per tile, S segments per pencil,
@@ -183,10 +190,6 @@ hipError_t launch_velocity_moments(int dtype, const void* f, int D, const int64_
                                    double* rho, double* mean, double* disp, hipStream_t s);
 hipError_t launch_velocity_distribution(int dtype, const void* f, int64_t nxs, int64_t nvs,
                                         double xvol, double* F, hipStream_t s);
-// f <- cb * b + cf * f over n elements of the storage type (TVD-RK stages)
-hipError_t launch_blend(int dtype, void* f, const void* b, double cb, double cf, int64_t n,
-                        hipStream_t s);
-
 constexpr int kDiagBlocks = 1024;
 
 }  // namespace slmpp

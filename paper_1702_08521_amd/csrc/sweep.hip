@@ -346,6 +346,36 @@ __device__ __forceinline__ void get(const double* s, vd2& v) {
   v.y = s[1];
 }
 
+// Result vector v of the elements at offset off from f: blended with
+// fblend and stored to fout or f (see SweepArgs; STAGE false: plain store
+// to f, for kernels that never run a TVD-RK stage); 16-byte aligned.
+template <bool STAGE = true, typename T, typename V>
+__device__ __forceinline__ void emit_vec(const SweepArgs& a, T* f, int64_t off, V v) {
+  constexpr int VN = sizeof(V) / sizeof(T);
+  if (!STAGE) {
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(f + off));
+    return;
+  }
+  if (a.fblend) {
+    const T cb = (T)a.cb, cf = (T)a.cf;
+    const V b = __builtin_nontemporal_load(
+        reinterpret_cast<const V*>(reinterpret_cast<const T*>(a.fblend) + off));
+#pragma unroll
+    for (int c = 0; c < VN; ++c) v[c] = vfma(cb, b[c], cf * v[c]);
+  }
+  T* dst = a.fout ? reinterpret_cast<T*>(a.fout) : f;
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(dst + off));
+}
+template <bool STAGE = true, typename T>
+__device__ __forceinline__ void emit_one(const SweepArgs& a, T* f, int64_t off, T v) {
+  if (!STAGE) {
+    f[off] = v;
+    return;
+  }
+  if (a.fblend) v = vfma((T)a.cb, reinterpret_cast<const T*>(a.fblend)[off], (T)a.cf * v);
+  (a.fout ? reinterpret_cast<T*>(a.fout) : f)[off] = v;
+}
+
 // a / b for non-negative 64-bit values, in 32-bit arithmetic when both fit
 __device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
   if (((a | b) >> 31) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
@@ -362,7 +392,7 @@ __device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
 // RC: cells per thread (0: runtime segment length).  WT: pencils per tile
 // as a compile-time constant (0: runtime), which turns the thread -> (pencil,
 // segment) and vector -> (row, column) maps into shifts and multiplies.
-template <typename T, int ORDER, int LIM, int RC, int WT>
+template <typename T, int ORDER, int LIM, int RC, int WT, bool STAGE = true>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& pl,
                                            const PencilEntry<T>* __restrict__ table,
                                            int64_t tile_index, unsigned char* smem) {
@@ -596,7 +626,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
       const int stepE = nthr * VN;
       const int dj = stepE / n, di = stepE - dj * n;
       int c = (tid * VN) / n, i = tid * VN - c * n;
-      V* dst = reinterpret_cast<V*>(f + gbase);
       for (int b0 = tid; b0 < nvec; b0 += KB * nthr) {
         V buf[KB];
 #pragma unroll
@@ -613,12 +642,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
         }
 #pragma unroll
         for (int k = 0; k < KB; ++k)
-          if (b0 + k * nthr < nvec) __builtin_nontemporal_store(buf[k], dst + b0 + k * nthr);
+          if (b0 + k * nthr < nvec) emit_vec<STAGE>(a, f, gbase + (int64_t)(b0 + k * nthr) * VN, buf[k]);
       }
     } else {
       for (int e2 = tid; e2 < total; e2 += nthr) {
         const int c = e2 / n, i = e2 - c * n;
-        f[gbase + e2] = res[c * P + G + i];
+        emit_one<STAGE>(a, f, gbase + e2, res[c * P + G + i]);
       }
     }
   } else if (vec_strided) {
@@ -626,25 +655,25 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
     const int c = tid % cpr;
     const int di = nthr / cpr;
     const int i0 = tid / cpr;
-    T* gp = f + gbase + (int64_t)i0 * a.inner + c * VN;
+    int64_t go = gbase + (int64_t)i0 * a.inner + c * VN;
     const int64_t gstep = (int64_t)di * a.inner;
-    for (int ib = i0; ib < n; ib += KB * di, gp += KB * gstep) {
+    for (int ib = i0; ib < n; ib += KB * di, go += KB * gstep) {
       V buf[KB];
 #pragma unroll
       for (int k = 0; k < KB; ++k)
         if (ib + k * di < n) buf[k] = *reinterpret_cast<const V*>(res + (ib + k * di + G) * W + c * VN);
 #pragma unroll
       for (int k = 0; k < KB; ++k)
-        if (ib + k * di < n)
-          __builtin_nontemporal_store(buf[k], reinterpret_cast<V*>(gp + k * gstep));
+        if (ib + k * di < n) emit_vec<STAGE>(a, f, go + k * gstep, buf[k]);
     }
   } else {
     const int c = tid % W;
     if (c < wv && (nthr % W) == 0) {
       const int64_t p = p0 + c;
       const int64_t o = udiv(p, a.inner);
-      T* gp = f + o * (int64_t)n * a.inner + (p - o * a.inner);
-      for (int i = tid / W; i < n; i += nthr / W) gp[(int64_t)i * a.inner] = res[(i + G) * W + c];
+      const int64_t go = o * (int64_t)n * a.inner + (p - o * a.inner);
+      for (int i = tid / W; i < n; i += nthr / W)
+        emit_one<STAGE>(a, f, go + (int64_t)i * a.inner, res[(i + G) * W + c]);
     }
   }
 }
@@ -871,7 +900,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
       if (vlim[k] < wv) {
         V v;
         get(tile + loff[k], v);
-        __builtin_nontemporal_store(v, reinterpret_cast<V*>(fc + gbase + goff0 + k * gstep));
+        emit_vec(a, fc, gbase + goff0 + k * gstep, v);
       }
     }
     if constexpr (MOM) {
@@ -1278,14 +1307,14 @@ __global__ void __launch_bounds__(256) batch_sweep_kernel(const BatchSweep* __re
     const PencilEntry<T>* tab = reinterpret_cast<const PencilEntry<T>*>(b.table);
     const int64_t t = item.tile;
     switch (b.order * 100 + pl.R) {
-      case 508: sweep_tile<T, 5, SLMPP_LIM_MPP, 8, 0>(a, pl, tab, t, smem); break;
-      case 512: sweep_tile<T, 5, SLMPP_LIM_MPP, 12, 0>(a, pl, tab, t, smem); break;
-      case 516: sweep_tile<T, 5, SLMPP_LIM_MPP, 16, 0>(a, pl, tab, t, smem); break;
-      case 708: sweep_tile<T, 7, SLMPP_LIM_MPP, 8, 0>(a, pl, tab, t, smem); break;
-      case 712: sweep_tile<T, 7, SLMPP_LIM_MPP, 12, 0>(a, pl, tab, t, smem); break;
-      case 716: sweep_tile<T, 7, SLMPP_LIM_MPP, 16, 0>(a, pl, tab, t, smem); break;
-      case 700: sweep_tile<T, 7, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, t, smem); break;
-      default: sweep_tile<T, 5, SLMPP_LIM_MPP, 0, 0>(a, pl, tab, t, smem); break;
+      case 508: sweep_tile<T, 5, SLMPP_LIM_MPP, 8, 0, false>(a, pl, tab, t, smem); break;
+      case 512: sweep_tile<T, 5, SLMPP_LIM_MPP, 12, 0, false>(a, pl, tab, t, smem); break;
+      case 516: sweep_tile<T, 5, SLMPP_LIM_MPP, 16, 0, false>(a, pl, tab, t, smem); break;
+      case 708: sweep_tile<T, 7, SLMPP_LIM_MPP, 8, 0, false>(a, pl, tab, t, smem); break;
+      case 712: sweep_tile<T, 7, SLMPP_LIM_MPP, 12, 0, false>(a, pl, tab, t, smem); break;
+      case 716: sweep_tile<T, 7, SLMPP_LIM_MPP, 16, 0, false>(a, pl, tab, t, smem); break;
+      case 700: sweep_tile<T, 7, SLMPP_LIM_MPP, 0, 0, false>(a, pl, tab, t, smem); break;
+      default: sweep_tile<T, 5, SLMPP_LIM_MPP, 0, 0, false>(a, pl, tab, t, smem); break;
     }
     __syncthreads();
   }
