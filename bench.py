@@ -107,9 +107,9 @@ def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ens
     storage = slmpp.F32 if dtype == "f32" else slmpp.F64
     stream = torch.cuda.Stream()
 
-    def make(st):
-        b = slmpp.Batch([slmpp.make_desc(s, st) for s in specs], [s["dt"] for s in specs],
-                        stream=stream)
+    def make(st, merged=False):
+        b = slmpp.Batch([slmpp.make_desc(dict(s, merge_kicks=merged), st) for s in specs],
+                        [s["dt"] for s in specs], stream=stream)
         for r, s in enumerate(specs):
             sx, gv = W.separable_factors(s)
             b.init_separable(r, sx, gv)
@@ -171,6 +171,22 @@ def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ens
         "autotune_s": round(tune_s, 3),
         "tile_widths": {str(k): v for k, v in sorted(widths.items())},
     }
+    # merged kicks (SLMPP_FLAG_MERGE_KICKS on every run): 10 steps per call
+    bm = make(storage, merged=True)
+    bm.step(10)
+    torch.cuda.synchronize()
+    ncall = max(1, steps // 10)
+    ev0.record(stream)
+    for _ in range(ncall):
+        bm.step(10)
+    ev1.record(stream)
+    ev1.synchronize()
+    merged_ms = ev0.elapsed_time(ev1) / (10 * ncall)
+    out["merged_kicks"] = {"steps_per_call": 10, "graph_ms_per_step": round(merged_ms, 4),
+                           "step_body_bytes": bm.step_bytes(),
+                           "step_speedup": round(graph_ms / merged_ms, 3)}
+    log(f"{log_prefix} merged kicks: {merged_ms:.3f} ms/step (10 steps per call)")
+    bm.close()
     if compare_fp64 and storage == slmpp.F32:
         # the same ensemble in FP64 storage from the same start, for the error
         # of FP32 storage and the FP64 rate on the same GPU

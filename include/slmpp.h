@@ -315,7 +315,10 @@ slmpp_status slmpp_batch_init_separable(slmpp_batch* b, int32_t run, const doubl
 /* Advance every run by nsteps steps of its own dt: the captured step graph
  * is replayed nsteps times (captured on first use, re-captured after
  * slmpp_batch_autotune).  The acceleration of each run is recomputed from
- * f first when an init call changed f. */
+ * f first when an init call changed f.  When the runs carry
+ * SLMPP_FLAG_MERGE_KICKS (all or none of them) the call merges kicks as
+ * slmpp_step does: an opening half-kick, nsteps - 1 step bodies ending in a
+ * full kick and a last one ending in a half-kick (three graphs). */
 slmpp_status slmpp_batch_step(slmpp_batch* b, int32_t nsteps);
 /* The same launches enqueued directly on the stream, without the graph. */
 slmpp_status slmpp_batch_step_eager(slmpp_batch* b, int32_t nsteps);
@@ -342,10 +345,11 @@ slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path);
  * next slmpp_batch_step).  Synchronises. */
 slmpp_status slmpp_batch_set_fast_min_cells(slmpp_batch* b, int64_t min_cells);
 
-/* Algorithmic HBM bytes of one step of the launch lists as built: every
- * pass over a run's f reads and writes it once (a two-axis kick pass counts
- * once for its two sweeps) and the velocity moment reads it once.  For
- * roofline figures; 0 for a NULL batch. */
+/* Algorithmic HBM bytes of one step of the launch lists as built (with
+ * merged kicks: of one step body): every pass over a run's f reads and
+ * writes it once (a two-axis kick pass counts once for its two sweeps) and
+ * the velocity moment reads it once.  For roofline figures; 0 for a NULL
+ * batch. */
 double slmpp_batch_step_bytes(const slmpp_batch* b);
 
 /* Tile width chosen for run r's sweep along array axis a (0..2D-1): the

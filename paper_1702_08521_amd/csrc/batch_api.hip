@@ -55,12 +55,16 @@ struct SlotDef {
   double frac;  // fraction of dt
 };
 
-std::vector<SlotDef> slot_defs(int Dmax, int& npre) {
+// Phases of a step, in groups of Dmax: opening half-kick v_1..v_Dmax,
+// x_Dmax..x_1 (full step), closing half-kick; with merged kicks also a
+// full kick (a closing and the next opening half-kick in one).
+std::vector<SlotDef> slot_defs(int Dmax, bool merged) {
   std::vector<SlotDef> s;
   for (int l = 0; l < Dmax; ++l) s.push_back({true, l, 0.5});
   for (int l = Dmax - 1; l >= 0; --l) s.push_back({false, l, 1.0});
-  npre = (int)s.size();
   for (int l = 0; l < Dmax; ++l) s.push_back({true, l, 0.5});
+  if (merged)
+    for (int l = 0; l < Dmax; ++l) s.push_back({true, l, 1.0});
   return s;
 }
 
@@ -74,6 +78,8 @@ struct Layout {
 };
 
 Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
+  const bool merged = !d.empty() && (d[0].flags & SLMPP_FLAG_MERGE_KICKS) != 0;
+  const int kicks = merged ? 3 : 2;  // velocity phases per axis
   Layout L{};
   const int n = (int)d.size();
   size_t off = 0;
@@ -103,13 +109,13 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
     // work items: every sweep of a step at the smallest tile width
     for (int a = 0; a < 2 * g.D; ++a) {
       const int64_t npen = g.ncell / g.dims[a];
-      L.max_items += (a >= g.D ? 2 : 1) * ((npen + kMinW - 1) / kMinW);
+      L.max_items += (a >= g.D ? kicks : 1) * ((npen + kMinW - 1) / kMinW);
     }
     L.nmitems += g.nxs;
     max_cells = std::max(max_cells, g.ncell);
     stage = std::max(stage, g.nxs + sumnv);
   }
-  L.max_sweeps = (int64_t)n * 3 * Dmax + 2 * (int64_t)n;  // plus two v_{D-1} tables per run
+  L.max_sweeps = (int64_t)n * (1 + kicks) * Dmax + 2 * (int64_t)n;
   L.runs = take(sizeof(BatchRun) * n);
   L.sweeps = take(sizeof(BatchSweep) * L.max_sweeps);
   L.items = take(sizeof(BatchItem) * std::max<int64_t>(L.max_items, 1));
@@ -138,8 +144,13 @@ slmpp_status check_batch(const slmpp_grid_desc* descs, int32_t nruns, std::strin
       msg = "all runs of a batch must share the storage type";
       return SLMPP_ERR_INVALID;
     }
-    if (descs[r].limiter != SLMPP_LIM_MPP || descs[r].flags != 0) {
-      msg = "batched runs use the SL-MPP scheme (SLMPP_LIM_MPP, flags 0)";
+    if (descs[r].limiter != SLMPP_LIM_MPP ||
+        (descs[r].flags != 0 && descs[r].flags != SLMPP_FLAG_MERGE_KICKS)) {
+      msg = "batched runs use the SL-MPP scheme (SLMPP_LIM_MPP; flags 0 or SLMPP_FLAG_MERGE_KICKS)";
+      return SLMPP_ERR_INVALID;
+    }
+    if (descs[r].flags != descs[0].flags) {
+      msg = "all runs of a batch must share the flags";
       return SLMPP_ERR_INVALID;
     }
     if (geom_of(descs[r]).nxs > kBatchMaxSpace) {
@@ -171,7 +182,8 @@ constexpr int64_t kFastMinCells = (int64_t)1 << 22;
 }  // namespace
 
 struct slmpp_batch {
-  int nruns = 0, dtype = SLMPP_F32, Dmax = 1, npre = 0;
+  int nruns = 0, dtype = SLMPP_F32, Dmax = 1;
+  bool merged = false;  // SLMPP_FLAG_MERGE_KICKS (every run)
   hipStream_t stream = nullptr;
   std::vector<slmpp_grid_desc> d;
   std::vector<RunGeom> g;
@@ -203,6 +215,7 @@ struct slmpp_batch {
   };
   std::vector<PlaneGroup> pgroups;
   double step_bytes = 0.0;  // algorithmic HBM bytes of one step as built
+  std::vector<double> slot_bytes;
   std::vector<void*> group_ptrs;
   int64_t fast_min_cells = kFastMinCells;
   std::vector<BatchSweep> sweeps;
@@ -212,8 +225,11 @@ struct slmpp_batch {
   std::vector<int> run_axis_width;   // run * 6 + axis
   int max_nxs = 1;
   size_t max_lds = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // captured graphs by kind: 0 a whole step; with merged kicks 1 the
+  // opening half-kick, 2 a step body ending in a full kick, 3 the last step
+  // body ending in a half-kick
+  hipGraph_t graph[4] = {};
+  hipGraphExec_t exec[4] = {};
   hipStream_t capture = nullptr;  // private stream the step graph is captured on
   bool field_valid = false;
   std::string err;
@@ -304,8 +320,7 @@ struct slmpp_batch {
     pgroups.clear();
     group_ptrs.clear();
     const double es = dtype == SLMPP_F64 ? 8.0 : 4.0;
-    step_bytes = 0.0;
-    for (int r = 0; r < nruns; ++r) step_bytes += es * (double)g[r].ncell;  // the moment
+    slot_bytes.assign(slots.size(), 0.0);
     run_axis_width.assign((size_t)nruns * 6, 0);
     max_lds = 0;
     void** dptrs = at<void*>(lay.ptrs);
@@ -384,7 +399,7 @@ struct slmpp_batch {
           }
           continue;
         }
-        if (has[r]) step_bytes += 2.0 * es * (double)g[r].ncell;
+        if (has[r]) slot_bytes[si] += 2.0 * es * (double)g[r].ncell;
         if (!has[r] || fast_min_cells < 0) continue;
         const SweepArgs& a = args[r];
         fplan[r] = plan_sweep(dtype, d[r].order, SLMPP_LIM_MPP, a.n, a.npen, a.inner, a.nfast, 0, 0);
@@ -469,7 +484,7 @@ struct slmpp_batch {
         pg.p.tiles *= (int64_t)rs.size();
         const size_t off = group_ptrs.size();
         for (int r : rs) group_ptrs.push_back(f[r]);
-        for (int r : rs) step_bytes += 2.0 * es * (double)g[r].ncell;
+        for (int r : rs) slot_bytes[si] += 2.0 * es * (double)g[r].ncell;
         for (int r : rs) group_ptrs.push_back(work + lay.tab2[r]);
         for (int r : rs) group_ptrs.push_back(work + lay.tab[r]);
         pg.a.fmulti = dptrs + off;
@@ -480,6 +495,15 @@ struct slmpp_batch {
       L.nitems = (int)items.size() - L.first_item;
       max_lds = std::max(max_lds, L.lds);
       launches.push_back(L);
+    }
+    // one step: the phases of a Strang step (with merged kicks a step body:
+    // x phases and a full kick), and the velocity moment
+    step_bytes = 0.0;
+    for (int r = 0; r < nruns; ++r) step_bytes += es * (double)g[r].ncell;
+    for (size_t si = 0; si < slots.size(); ++si) {
+      const bool in_step = merged ? (int)si >= Dmax && ((int)si < 2 * Dmax || (int)si >= 3 * Dmax)
+                                  : (int)si < 3 * Dmax;
+      if (in_step) step_bytes += slot_bytes[si];
     }
     if ((int64_t)items.size() > lay.max_items || (int64_t)sweeps.size() > lay.max_sweeps ||
         (int64_t)group_ptrs.size() > 4 * lay.max_sweeps)
@@ -509,10 +533,12 @@ struct slmpp_batch {
   }
 
   void drop_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
+    for (int k = 0; k < 4; ++k) {
+      if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+      exec[k] = nullptr;
+      graph[k] = nullptr;
+    }
   }
 
   hipError_t enqueue_slot(int si, hipStream_t s) {
@@ -544,11 +570,34 @@ struct slmpp_batch {
     return e;
   }
 
-  hipError_t enqueue_step(hipStream_t s) {
+  hipError_t enqueue_range(int first, int count, hipStream_t s) {
     hipError_t e = hipSuccess;
-    for (int si = 0; si < npre && e == hipSuccess; ++si) e = enqueue_slot(si, s);
+    for (int si = first; si < first + count && e == hipSuccess; ++si) e = enqueue_slot(si, s);
+    return e;
+  }
+
+  // kind: see graph[]
+  hipError_t enqueue_kind(int kind, hipStream_t s) {
+    const int K = Dmax;
+    if (kind == 1) return enqueue_range(0, K, s);
+    hipError_t e = kind == 0 ? enqueue_range(0, K, s) : hipSuccess;
+    if (e == hipSuccess) e = enqueue_range(K, K, s);
     if (e == hipSuccess) e = enqueue_field(s);
-    for (int si = npre; si < (int)slots.size() && e == hipSuccess; ++si) e = enqueue_slot(si, s);
+    if (e == hipSuccess) e = enqueue_range(kind == 2 ? 3 * K : 2 * K, K, s);
+    return e;
+  }
+
+  // the kinds of a call of nsteps, in order
+  template <typename F>
+  hipError_t for_each_kind(int32_t nsteps, F&& run) {
+    if (!merged) {
+      hipError_t e = hipSuccess;
+      for (int32_t i = 0; i < nsteps && e == hipSuccess; ++i) e = run(0);
+      return e;
+    }
+    hipError_t e = run(1);
+    for (int32_t i = 0; i + 1 < nsteps && e == hipSuccess; ++i) e = run(2);
+    if (e == hipSuccess) e = run(3);
     return e;
   }
 
@@ -644,7 +693,8 @@ slmpp_status slmpp_batch_create(const slmpp_grid_desc* descs, const double* dts,
       b->runs.push_back(R);
       for (int64_t ix = 0; ix < G.nxs; ++ix) mitems.push_back(make_int2(r, (int)ix));
     }
-    b->slots = slot_defs(b->Dmax, b->npre);
+    b->merged = (dv[0].flags & SLMPP_FLAG_MERGE_KICKS) != 0;
+    b->slots = slot_defs(b->Dmax, b->merged);
     hipError_t e = hipMemcpyAsync(b->at<BatchRun>(lay.runs), b->runs.data(),
                                   sizeof(BatchRun) * b->runs.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -715,33 +765,43 @@ slmpp_status slmpp_batch_step(slmpp_batch* b, int32_t nsteps) {
   if (nsteps < 1) return b->fail(SLMPP_ERR_INVALID, "nsteps must be >= 1");
   slmpp_status st = b->ensure_field();
   if (st != SLMPP_OK) return st;
-  if (!b->exec) {
-    // captured on a private stream (the caller's may be the null stream,
-    // which cannot be captured); replayed on the caller's stream
-    hipError_t e = hipSuccess;
-    if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-    if (e != hipSuccess) return b->hip_fail(e, "capture stream");
-    e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) return b->hip_fail(e, "begin capture");
-    hipError_t el = b->enqueue_step(b->capture);
-    hipGraph_t gr = nullptr;
-    e = hipStreamEndCapture(b->capture, &gr);
-    if (el != hipSuccess) {
-      if (gr) (void)hipGraphDestroy(gr);
-      return b->hip_fail(el, "step capture");
+  // graphs are captured on first use on a private stream (the caller's may
+  // be the null stream, which cannot be captured) and replayed on the
+  // caller's stream
+  const char* what = nullptr;
+  hipError_t e = b->for_each_kind(nsteps, [&](int kind) -> hipError_t {
+    if (!b->exec[kind]) {
+      hipError_t r = hipSuccess;
+      if (!b->capture) r = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+      if (r != hipSuccess) {
+        what = "capture stream";
+        return r;
+      }
+      r = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+      if (r != hipSuccess) {
+        what = "begin capture";
+        return r;
+      }
+      const hipError_t el = b->enqueue_kind(kind, b->capture);
+      hipGraph_t gr = nullptr;
+      r = hipStreamEndCapture(b->capture, &gr);
+      if (el != hipSuccess || r != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        what = "step capture";
+        return el != hipSuccess ? el : r;
+      }
+      b->graph[kind] = gr;
+      r = hipGraphInstantiate(&b->exec[kind], gr, nullptr, nullptr, 0);
+      if (r != hipSuccess) {
+        b->drop_graph();
+        what = "graph instantiate";
+        return r;
+      }
     }
-    if (e != hipSuccess) return b->hip_fail(e, "end capture");
-    b->graph = gr;
-    e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      b->drop_graph();
-      return b->hip_fail(e, "graph instantiate");
-    }
-  }
-  for (int32_t i = 0; i < nsteps; ++i) {
-    hipError_t e = hipGraphLaunch(b->exec, b->stream);
-    if (e != hipSuccess) return b->hip_fail(e, "graph launch");
-  }
+    what = "graph launch";
+    return hipGraphLaunch(b->exec[kind], b->stream);
+  });
+  if (e != hipSuccess) return b->hip_fail(e, what ? what : "batch step");
   return SLMPP_OK;
 }
 
@@ -750,10 +810,8 @@ slmpp_status slmpp_batch_step_eager(slmpp_batch* b, int32_t nsteps) {
   if (nsteps < 1) return b->fail(SLMPP_ERR_INVALID, "nsteps must be >= 1");
   slmpp_status st = b->ensure_field();
   if (st != SLMPP_OK) return st;
-  for (int32_t i = 0; i < nsteps; ++i) {
-    hipError_t e = b->enqueue_step(b->stream);
-    if (e != hipSuccess) return b->hip_fail(e, "batch step");
-  }
+  hipError_t e = b->for_each_kind(nsteps, [&](int kind) { return b->enqueue_kind(kind, b->stream); });
+  if (e != hipSuccess) return b->hip_fail(e, "batch step");
   return SLMPP_OK;
 }
 

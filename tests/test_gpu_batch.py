@@ -235,6 +235,41 @@ def test_batch_fast_groups_match_oracle_and_tile_launch(S, storage):
     b.close()
 
 
+@pytest.mark.parametrize("storage", [0, 1])
+def test_batch_merged_kicks_match_oracle(S, storage):
+    """SLMPP_FLAG_MERGE_KICKS on every run: a call of n steps is an opening
+    half-kick, n - 1 bodies ending in a full kick and a last body ending in
+    a half-kick, as the oracle does for one run.  Graph replay with the
+    grouped launches against eager launches with the tile launch only, bit
+    for bit; two calls in a row."""
+    specs = [dict(s, merge_kicks=True) for s in same_geometry_ensemble()]
+    say(f"case batch merged kicks storage={storage}")
+    a = _batch(S, specs, storage)
+    a.set_fast_min_cells(1)
+    b = _batch(S, specs, storage)
+    b.set_fast_min_cells(-1)
+    a.step(5)
+    b.step_eager(5)
+    a.step(3)
+    b.step_eager(3)
+    tol = 1e-12 if storage == 0 else 1e-5
+    for r, s in enumerate(specs):
+        f0 = None
+        if storage == 1:
+            sx, gv = W.separable_factors(s)
+            f0 = O.init_separable(O.make_grid(s), sx, gv).astype(np.float32).astype(np.float64)
+        run = O.Run(s, f0)
+        run.step(s["dt"], 5)
+        run.step(s["dt"], 3)
+        ga, gb = a.get_f(r), b.get_f(r)
+        err = l1rel(ga, run.f)
+        say(f"  run {r} {s['name']} D={s['D']}: L1 rel {err:.3e}")
+        assert np.array_equal(ga, gb), r
+        assert err <= tol, (r, err)
+    a.close()
+    b.close()
+
+
 def test_batch_error_paths(S):
     specs = ensemble()[:2]
     b = _batch(S, specs, 0)
