@@ -339,10 +339,14 @@ slmpp_status slmpp_batch_autotune(slmpp_batch* b, const char* cache_path);
  * to at least min_cells (default 4194304); so are the v_{D-1} and v_D
  * sweeps of the kicks of runs with one velocity-plane geometry that the
  * two-axis pass of slmpp_step takes (see SLMPP_FLAG_SEPARATE_KICKS), as
- * one pass in the v_D phase.  The other sweeps stay in the grouped tile
- * launch.  min_cells < 0: never.  All forms give the same results bit for
- * bit.  Rebuilds the launch lists (the step graph is captured again on the
- * next slmpp_batch_step).  Synchronises. */
+ * one pass in the v_D phase.  A grouped x_1 phase whose tiles lie within
+ * velocity blocks also leaves the tile row sums of the velocity moment
+ * (summed per run afterwards instead of a pass over f).  The other sweeps
+ * stay in the grouped tile launch.  min_cells < 0: never.  Every sweep
+ * gives the same results in all forms, bit for bit; the fused moment sums
+ * in another order (equal to rounding).  Rebuilds the launch lists (the
+ * step graph is captured again on the next slmpp_batch_step).
+ * Synchronises. */
 slmpp_status slmpp_batch_set_fast_min_cells(slmpp_batch* b, int64_t min_cells);
 
 /* Algorithmic HBM bytes of one step of the launch lists as built (with

@@ -90,6 +90,29 @@ __global__ void __launch_bounds__(256) batch_moment_kernel(const BatchRun* __res
   }
 }
 
+// rho of every listed run from the tile row sums its x_1 sweep left
+// (grid.y = list entry): the row sums of one spatial cell added in tile
+// order, compensated, in two interleaved accumulators.
+__global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchReduce* __restrict__ list) {
+  const BatchReduce& b = list[blockIdx.y];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= b.ncol * b.n) return;
+  const int64_t c = g / b.n;
+  const int i = (int)(g - c * b.n);
+  const double* p = b.part + c * b.nsub * b.n + i;
+  KSum acc0{0.0, 0.0}, acc1{0.0, 0.0};
+  int64_t q = 0;
+  for (; q + 1 < b.nsub; q += 2) {
+    const double x0 = p[q * b.n], x1 = p[(q + 1) * b.n];
+    kadd(acc0, x0);
+    kadd(acc1, x1);
+  }
+  if (q < b.nsub) kadd(acc0, p[q * b.n]);
+  kadd(acc0, acc1.s);
+  acc0.c += acc1.c;
+  b.rho[(int64_t)i * b.ncol + c] = b.dvol * (acc0.s + acc0.c);
+}
+
 // Laplacian symbol times Delta^2 of the App. C stencils of order 2, 4, 6
 __device__ __forceinline__ double lap_symbol(double th, int order) {
   const double a = sin(0.5 * th), b = sin(th), c = sin(1.5 * th);
@@ -240,6 +263,14 @@ hipError_t launch_batch_moment(int dtype, const BatchRun* runs, const int2* item
     hipLaunchKernelGGL(batch_moment_kernel<double>, dim3(grid), dim3(256), 0, s, runs, items, nitems);
   else
     hipLaunchKernelGGL(batch_moment_kernel<float>, dim3(grid), dim3(256), 0, s, runs, items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const BatchReduce* list, int nlist, int64_t max_cells,
+                               hipStream_t s) {
+  if (nlist <= 0 || max_cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((max_cells + 255) / 256), nlist), dim3(256),
+                     0, s, list);
   return hipGetLastError();
 }
 

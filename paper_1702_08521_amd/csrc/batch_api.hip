@@ -73,8 +73,8 @@ constexpr int kMinW = 8;
 
 struct Layout {
   std::vector<size_t> rho, phi, acc, tab, tab2;
-  size_t runs, sweeps, items, mitems, ptrs, scratch, stage, total;
-  int64_t max_sweeps, max_items, nmitems, stage_doubles;
+  size_t runs, sweeps, items, mitems, mitems2, mom, reduce, ptrs, scratch, stage, total;
+  int64_t max_sweeps, max_items, nmitems, stage_doubles, mom_doubles;
 };
 
 Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
@@ -92,6 +92,7 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
   int64_t max_cells = 1, stage = 1;
   L.max_items = 0;
   L.nmitems = 0;
+  L.mom_doubles = 0;
   for (int r = 0; r < n; ++r) {
     const RunGeom g = geom_of(d[r]);
     Dmax = std::max(Dmax, g.D);
@@ -112,6 +113,7 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
       L.max_items += (a >= g.D ? kicks : 1) * ((npen + kMinW - 1) / kMinW);
     }
     L.nmitems += g.nxs;
+    L.mom_doubles += g.ncell / 64 + 1;  // row sums of a fused x_1 sweep (tiles of >= 64 pencils)
     max_cells = std::max(max_cells, g.ncell);
     stage = std::max(stage, g.nxs + sumnv);
   }
@@ -120,6 +122,9 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
   L.sweeps = take(sizeof(BatchSweep) * L.max_sweeps);
   L.items = take(sizeof(BatchItem) * std::max<int64_t>(L.max_items, 1));
   L.mitems = take(sizeof(int2) * std::max<int64_t>(L.nmitems, 1));
+  L.mitems2 = take(sizeof(int2) * std::max<int64_t>(L.nmitems, 1));  // runs without a fused moment
+  L.mom = take(sizeof(double) * L.mom_doubles);
+  L.reduce = take(sizeof(BatchReduce) * n);
   // f and table pointers of persistent launches over several runs
   L.ptrs = take(sizeof(void*) * 4 * L.max_sweeps);
   L.scratch = take(8 * max_cells);
@@ -206,6 +211,11 @@ struct slmpp_batch {
     SweepPlan p;  // tiles over all runs of the group
   };
   std::vector<FastGroup> groups;
+  // velocity moment fused into the x_1 sweep of fast groups: the runs'
+  // row-sum reductions, and the moment items of the other runs
+  std::vector<BatchReduce> reduce;
+  std::vector<int2> mitems2;
+  int64_t max_reduce_cells = 0;
   // runs of one plane geometry whose v_{D-1} and v_D sweeps of a kick run
   // as one kick_plane_kernel launch (in the v_D phase)
   struct PlaneGroup {
@@ -319,6 +329,11 @@ struct slmpp_batch {
     groups.clear();
     pgroups.clear();
     group_ptrs.clear();
+    reduce.clear();
+    max_reduce_cells = 0;
+    std::vector<char> mom_fused((size_t)nruns, 0);
+    std::vector<int64_t> rowsums((size_t)nruns, 0);
+    double* mom_next = at<double>(lay.mom);
     const double es = dtype == SLMPP_F64 ? 8.0 : 4.0;
     slot_bytes.assign(slots.size(), 0.0);
     run_axis_width.assign((size_t)nruns * 6, 0);
@@ -423,6 +438,28 @@ struct slmpp_batch {
         fg.a.fmulti = dptrs + off;
         fg.a.tmulti = const_cast<const void* const*>(dptrs + off + rs.size());
         for (int r : rs) grouped[r] = 1;
+        // the x_1 phase of runs whose tiles lie within velocity blocks
+        // also leaves the row sums of the velocity moment
+        const SweepPlan& fp = fplan[r0];
+        const bool x1 = !slots[si].vel && slots[si].l == 0;
+        if (x1 && (fp.W == 64 || fp.W == 128) && fg.a.inner > 1 && g[r0].nvs % fp.W == 0) {
+          fg.a.mom = mom_next;
+          for (size_t k = 0; k < rs.size(); ++k) {
+            const int r = rs[k];
+            BatchReduce br{};
+            br.part = mom_next + (int64_t)k * fp.tiles * fg.a.n;
+            br.rho = at<double>(lay.rho[r]);
+            br.n = fg.a.n;
+            br.ncol = g[r].nxs / fg.a.n;
+            br.nsub = g[r].nvs / fp.W;
+            br.dvol = runs[r].dvol;
+            reduce.push_back(br);
+            mom_fused[r] = 1;
+            rowsums[r] = fp.tiles * fg.a.n;
+            max_reduce_cells = std::max(max_reduce_cells, g[r].nxs);
+          }
+          mom_next += (int64_t)rs.size() * fp.tiles * fg.a.n;
+        }
         groups.push_back(fg);
         ++L.ngroups;
       }
@@ -497,9 +534,11 @@ struct slmpp_batch {
       launches.push_back(L);
     }
     // one step: the phases of a Strang step (with merged kicks a step body:
-    // x phases and a full kick), and the velocity moment
+    // x phases and a full kick), and the velocity moment (a read of f, or
+    // the row sums written and read back when fused into the x_1 phase)
     step_bytes = 0.0;
-    for (int r = 0; r < nruns; ++r) step_bytes += es * (double)g[r].ncell;
+    for (int r = 0; r < nruns; ++r)
+      step_bytes += mom_fused[r] ? 16.0 * (double)rowsums[r] : es * (double)g[r].ncell;
     for (size_t si = 0; si < slots.size(); ++si) {
       const bool in_step = merged ? (int)si >= Dmax && ((int)si < 2 * Dmax || (int)si >= 3 * Dmax)
                                   : (int)si < 3 * Dmax;
@@ -525,6 +564,16 @@ struct slmpp_batch {
                          hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && !group_ptrs.empty())
       e = hipMemcpyAsync(dptrs, group_ptrs.data(), sizeof(void*) * group_ptrs.size(),
+                         hipMemcpyHostToDevice, stream);
+    mitems2.clear();
+    for (int r = 0; r < nruns && !reduce.empty(); ++r)
+      if (!mom_fused[r])
+        for (int64_t ix = 0; ix < g[r].nxs; ++ix) mitems2.push_back(make_int2(r, (int)ix));
+    if (e == hipSuccess && !reduce.empty())
+      e = hipMemcpyAsync(at<BatchReduce>(lay.reduce), reduce.data(), sizeof(BatchReduce) * reduce.size(),
+                         hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !mitems2.empty())
+      e = hipMemcpyAsync(at<int2>(lay.mitems2), mitems2.data(), sizeof(int2) * mitems2.size(),
                          hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "upload of batch work lists");
@@ -563,9 +612,17 @@ struct slmpp_batch {
     return e;
   }
 
-  hipError_t enqueue_field(hipStream_t s) {
-    hipError_t e = launch_batch_moment(dtype, at<BatchRun>(lay.runs), at<int2>(lay.mitems),
-                                       (int)lay.nmitems, s);
+  // after_x1: right after the x_1 phase of a step, whose fused groups left
+  // row sums; otherwise the moment of every run from f
+  hipError_t enqueue_field(hipStream_t s, bool after_x1 = false) {
+    hipError_t e;
+    if (after_x1 && !reduce.empty()) {
+      e = launch_batch_moment(dtype, at<BatchRun>(lay.runs), at<int2>(lay.mitems2), (int)mitems2.size(), s);
+      if (e == hipSuccess)
+        e = launch_batch_reduce(at<BatchReduce>(lay.reduce), (int)reduce.size(), max_reduce_cells, s);
+    } else {
+      e = launch_batch_moment(dtype, at<BatchRun>(lay.runs), at<int2>(lay.mitems), (int)lay.nmitems, s);
+    }
     if (e == hipSuccess) e = launch_batch_poisson(at<BatchRun>(lay.runs), nruns, max_nxs, s);
     return e;
   }
@@ -582,7 +639,7 @@ struct slmpp_batch {
     if (kind == 1) return enqueue_range(0, K, s);
     hipError_t e = kind == 0 ? enqueue_range(0, K, s) : hipSuccess;
     if (e == hipSuccess) e = enqueue_range(K, K, s);
-    if (e == hipSuccess) e = enqueue_field(s);
+    if (e == hipSuccess) e = enqueue_field(s, true);
     if (e == hipSuccess) e = enqueue_range(kind == 2 ? 3 * K : 2 * K, K, s);
     return e;
   }

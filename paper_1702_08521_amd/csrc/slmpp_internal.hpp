@@ -133,6 +133,17 @@ struct BatchRun {
   int32_t D;
   int32_t poisson_order;
 };
+// rho of one run from the tile row sums of its x_1 sweep (fused moment):
+// rho[i * ncol + c] = dvol * sum_{q < nsub} part[(c * nsub + q) * n + i]
+struct BatchReduce {
+  const double* part;
+  double* rho;
+  int64_t ncol, nsub;
+  int32_t n, pad;
+  double dvol;
+};
+hipError_t launch_batch_reduce(const BatchReduce* list, int nlist, int64_t max_cells,
+                               hipStream_t s);
 hipError_t launch_batch_tables(int dtype, const BatchSweep* sweeps, int nsweeps, int max_count,
                                hipStream_t s);
 hipError_t launch_batch_sweeps(int dtype, const BatchSweep* sweeps, const BatchItem* items,

@@ -214,25 +214,32 @@ def test_batch_fast_groups_match_oracle_and_tile_launch(S, storage):
     b.step(nsteps)
     refs = _oracle_runs(specs, storage, nsteps)
     tol = 1e-12 if storage == 0 else 1e-5
+    # the sweeps agree bit for bit; the velocity moment of grouped x_1
+    # sweeps is summed from tile row sums (another rounding order)
+    same = 1e-14 if storage == 0 else 1e-6
     for r, (s, ref) in enumerate(zip(specs, refs)):
         ga, gb = a.get_f(r), b.get_f(r)
         err = l1rel(ga, ref)
-        say(f"  run {r} {s['name']} D={s['D']} order={s['order']}: L1 rel {err:.3e}")
-        assert np.array_equal(ga, gb), (r, np.abs(ga - gb).max())
+        say(f"  run {r} {s['name']} D={s['D']} order={s['order']}: L1 rel {err:.3e}, "
+            f"grouped vs tiles {l1rel(ga, gb):.1e}")
+        assert l1rel(ga, gb) <= same, (r, np.abs(ga - gb).max())
         assert err <= tol, (r, s["name"], err)
     assert changed > 0
-    # the eager form of the grouped launches, and back to the default
-    a.step_eager(2)
-    b.step(2)
+    # the eager form of the grouped launches against its graph, bit for bit
+    c = _batch(S, specs, storage)
+    c.set_fast_min_cells(1)
+    c.step_eager(nsteps)
     for r in range(len(specs)):
-        assert np.array_equal(a.get_f(r), b.get_f(r)), r
+        assert np.array_equal(a.get_f(r), c.get_f(r)), r
+    # back to the default grouping
     a.set_fast_min_cells(4 << 20)
     a.step(1)
     b.step(1)
     for r in range(len(specs)):
-        assert np.array_equal(a.get_f(r), b.get_f(r)), r
+        assert l1rel(a.get_f(r), b.get_f(r)) <= same, r
     a.close()
     b.close()
+    c.close()
 
 
 @pytest.mark.parametrize("storage", [0, 1])
@@ -240,8 +247,8 @@ def test_batch_merged_kicks_match_oracle(S, storage):
     """SLMPP_FLAG_MERGE_KICKS on every run: a call of n steps is an opening
     half-kick, n - 1 bodies ending in a full kick and a last body ending in
     a half-kick, as the oracle does for one run.  Graph replay with the
-    grouped launches against eager launches with the tile launch only, bit
-    for bit; two calls in a row."""
+    grouped launches against eager launches with the tile launch only (to
+    the rounding order of the fused moment); two calls in a row."""
     specs = [dict(s, merge_kicks=True) for s in same_geometry_ensemble()]
     say(f"case batch merged kicks storage={storage}")
     a = _batch(S, specs, storage)
@@ -264,7 +271,7 @@ def test_batch_merged_kicks_match_oracle(S, storage):
         ga, gb = a.get_f(r), b.get_f(r)
         err = l1rel(ga, run.f)
         say(f"  run {r} {s['name']} D={s['D']}: L1 rel {err:.3e}")
-        assert np.array_equal(ga, gb), r
+        assert l1rel(ga, gb) <= (1e-14 if storage == 0 else 1e-6), r
         assert err <= tol, (r, err)
     a.close()
     b.close()
