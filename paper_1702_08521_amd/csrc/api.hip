@@ -27,7 +27,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t rho, phi, accel, green, bufA, bufB, tw, partials, diagfield, table, table2, stage, mom, rkbuf,
-      isoA, isoB, isoG, tw2, total;
+      isoA, isoB, isoG, tw2, prun, total;
   int64_t stage_doubles, mom_doubles;
 };
 
@@ -85,6 +85,8 @@ Layout layout_of(const slmpp_grid_desc& d) {
   L.isoB = take(sizeof(double2) * ms);
   L.isoG = take(sizeof(double) * ms);
   L.tw2 = take(iso ? sizeof(double2) * 2 * sumnx : 0);
+  // small periodic grids: the field of the context in one workgroup
+  L.prun = take(sizeof(BatchRun));
   L.total = off;
   return L;
 }
@@ -207,6 +209,9 @@ struct slmpp_ctx {
   double2* tw2() { return reinterpret_cast<double2*>(work + lay.tw2); }
   int64_t tw2_off[3]{};
   bool isolated = false;  // SLMPP_FLAG_ISOLATED
+  // periodic grid of at most kBatchMaxSpace cells: the context's own field
+  // solve runs as one workgroup in LDS (the batched ensembles' kernel)
+  bool small_field = false;
   void* rkbuf() { return work + lay.rkbuf; }
   bool rk = false;  // SLMPP_FLAG_RK3
   int mom_w = 64;  // tile width of the last fused x_1 sweep
@@ -434,7 +439,10 @@ struct slmpp_ctx {
 
   slmpp_status poisson(const double* rho_dev, double* phi_dev, double* accel_dev) {
     hipError_t e = tic(3, 8.0 * nxs * (2 + D), 0.0);
-    if (e == hipSuccess && isolated)
+    const bool own = rho_dev == rho() && (!phi_dev || phi_dev == phi()) && accel_dev == accel();
+    if (e == hipSuccess && small_field && own)
+      e = launch_batch_poisson(reinterpret_cast<const BatchRun*>(work + lay.prun), 1, (int)nxs, stream);
+    else if (e == hipSuccess && isolated)
       e = launch_poisson_isolated(rho_dev, phi_dev ? phi_dev : phi(), accel_dev, isoA(), isoB(),
                                   tw2(), tw2_off, isoG(), d.nx, hx, d.poisson_order, stream);
     else if (e == hipSuccess)
@@ -642,6 +650,27 @@ slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_d
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     c->isolated = (desc->flags & SLMPP_FLAG_ISOLATED) != 0;
     if (e == hipSuccess && c->isolated) e = iso_setup(c, *desc);
+    if (e == hipSuccess && !c->isolated && c->nxs <= kBatchMaxSpace) {
+      BatchRun R{};
+      R.f = c->f;
+      R.rho = c->rho();
+      R.phi = c->phi();
+      R.accel = c->accel();
+      R.nxs = c->nxs;
+      R.nvs = c->nvs;
+      R.dvol = 1.0;
+      for (int l = 0; l < 3; ++l) {
+        R.nx[l] = l < c->D ? desc->nx[l] : 1;
+        R.h[l] = l < c->D ? c->hx[l] : 1.0;
+      }
+      R.kappa = desc->kappa;
+      R.D = c->D;
+      R.poisson_order = desc->poisson_order;
+      e = hipMemcpyAsync(c->work + c->lay.prun, &R, sizeof(R), hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = prepare_batch_kernels(desc->storage, 0, (int)c->nxs);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      c->small_field = e == hipSuccess;
+    }
     if (e != hipSuccess) {
       g_error = std::string("upload of field tables: ") + hipGetErrorString(e);
       delete c;
@@ -657,7 +686,7 @@ slmpp_status slmpp_create(const slmpp_grid_desc* desc, void* f_dev, void* work_d
 
 slmpp_status slmpp_destroy(slmpp_ctx* ctx) {
   if (!ctx) return SLMPP_ERR_INVALID;
-  if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return SLMPP_OK;
