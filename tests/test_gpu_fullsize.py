@@ -128,16 +128,17 @@ def test_fullsize_jeans_independent_of_x2_x3(S):
     ctx.close()
 
 
-@pytest.mark.parametrize("which", ["landau_3d3v_48", "jeans_3d3v_32"])
+@pytest.mark.parametrize("which", ["landau_3d3v_48", "jeans_3d3v_32", "landau_3d3v_48_f64"])
 def test_fullsize_kick_velocity_blocks(S, which):
     """A velocity kick at the benchmark size (v1 sweep, then the two-axis
     pass over the (v2, v3) planes), checked on the whole velocity block of
     sampled spatial cells: the kick acts on each block alone with that
-    cell's acceleration.  The oracle rounds to FP32 after each sweep, as the
-    GPU stores between sweeps (in HBM after v1, in LDS after v2)."""
-    spec = W.landau_3d3v(n=48, order=7) if which == "landau_3d3v_48" else W.jeans_3d3v(n=32, order=5)
+    cell's acceleration.  In FP32 the oracle rounds to FP32 after each sweep,
+    as the GPU stores between sweeps (in HBM after v1, in LDS after v2)."""
+    spec = W.jeans_3d3v(n=32, order=5) if which == "jeans_3d3v_32" else W.landau_3d3v(n=48, order=7)
+    fp64 = which.endswith("_f64")
     D = spec["D"]
-    ctx = S.Context(S.make_desc(spec, S.F32))
+    ctx = S.Context(S.make_desc(spec, S.F64 if fp64 else S.F32))
     s, gv = W.separable_factors(spec)
     ctx.init_f_separable(s, gv)
     ctx.field()
@@ -163,10 +164,11 @@ def test_fullsize_kick_velocity_blocks(S, which):
             xi = O.xi(acc[l * nxs + ix], dt, h)
             O.sweep_lines(ref, l, xi, order=spec["order"], limiter=spec["limiter"],
                           alpha=spec["alpha"], bc=spec["v_bc"])
-            ref = ref.astype(np.float32).astype(np.float64)
+            if not fp64:
+                ref = ref.astype(np.float32).astype(np.float64)
         got = f[c].double().cpu().numpy()
         err = np.abs(got - ref).max() / np.abs(ref).max()
         worst = max(worst, err)
-        assert err <= 64 * 2.0 ** -24, (c, err)
+        assert err <= (1e-13 if fp64 else 64 * 2.0 ** -24), (c, err)
     say(f"  worst block error {worst:.3e} (FP32 ulps of max: {worst / 2.0 ** -24:.1f})")
     ctx.close()
