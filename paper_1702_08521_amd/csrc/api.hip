@@ -453,6 +453,16 @@ struct slmpp_ctx {
     return SLMPP_OK;
   }
 
+  // one Strang step with the current field: kick, x sweeps, field, kick
+  slmpp_status step_body(double dt) {
+    slmpp_status st = kick(0.5 * dt);
+    bool fused = false;
+    for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l) st = sweep(l, dt, nullptr, l == 0, &fused);
+    if (st == SLMPP_OK) st = fused ? field_from_rowsums() : field();
+    if (st == SLMPP_OK) st = kick(0.5 * dt);
+    return st;
+  }
+
   // the field after an x_1 sweep that left its tile row sums (see sweep)
   slmpp_status field_from_rowsums() {
     double dvol = 1.0;
@@ -861,11 +871,7 @@ slmpp_status slmpp_step(slmpp_ctx* c, double dt, int32_t nsteps) {
   for (int32_t it = 0; it < nsteps; ++it) {
     slmpp_status st = SLMPP_OK;
     if (!c->field_valid) st = c->field();
-    if (st == SLMPP_OK) st = c->kick(0.5 * dt);
-    bool fused = false;
-    for (int l = D - 1; l >= 0 && st == SLMPP_OK; --l) st = c->sweep(l, dt, nullptr, l == 0, &fused);
-    if (st == SLMPP_OK) st = fused ? c->field_from_rowsums() : c->field();
-    if (st == SLMPP_OK) st = c->kick(0.5 * dt);
+    if (st == SLMPP_OK) st = c->step_body(dt);
     if (st != SLMPP_OK) {
       c->field_valid = false;
       return st;
