@@ -332,7 +332,8 @@ struct slmpp_ctx {
       s.rk = 1;
       s.nfast = 0;  // no integer shift in an RK stage
     }
-    SweepPlan p = plan_sweep(d.storage, d.order, d.limiter, s.n, s.npen, inner, s.nfast);
+    SweepPlan p = plan_sweep(d.storage, d.order, d.limiter, s.n, s.npen, inner, s.nfast, 0, 0,
+                             fuse_moment && !rk && a == 0);
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
     if (fuse_moment && !rk && a == 0 && p.fast && (p.W == 64 || p.W == 128) && inner > 1 &&

@@ -417,7 +417,8 @@ struct slmpp_batch {
         if (has[r]) slot_bytes[si] += 2.0 * es * (double)g[r].ncell;
         if (!has[r] || fast_min_cells < 0) continue;
         const SweepArgs& a = args[r];
-        fplan[r] = plan_sweep(dtype, d[r].order, SLMPP_LIM_MPP, a.n, a.npen, a.inner, a.nfast, 0, 0);
+        fplan[r] = plan_sweep(dtype, d[r].order, SLMPP_LIM_MPP, a.n, a.npen, a.inner, a.nfast, 0, 0,
+                              !slots[si].vel && slots[si].l == 0);
         if (fplan[r].fast) by_key[fast_key(d[r].order, a)].push_back(r);
       }
       for (const auto& kv : by_key) {

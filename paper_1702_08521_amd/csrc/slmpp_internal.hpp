@@ -64,9 +64,10 @@ struct SweepPlan {
   int64_t tiles;
 };
 
-// Plans a sweep launch for the given sizes (dtype: SLMPP_F64/F32).
+// Plans a sweep launch for the given sizes (dtype: SLMPP_F64/F32); moment:
+// the sweep also leaves tile row sums (SweepArgs::mom) when its plan allows.
 SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen, int64_t inner,
-                     int32_t nfast, int W_override = 0, int S_override = 0);
+                     int32_t nfast, int W_override = 0, int S_override = 0, bool moment = false);
 
 // Enqueue the pencil table (table_count entries, one per distinct speed;
 // `table` is device scratch of pencil_table_bytes()), then the sweep.

@@ -1230,21 +1230,27 @@ hipError_t launch_fast(const SweepArgs& a, const SweepPlan& p, const void* table
 
 template <typename T, int ORDER, int RC>
 hipError_t launch_w(const SweepArgs& a, const SweepPlan& p, const void* table, hipStream_t s) {
-  if (p.fast) {
-    if (a.inner == 1) return launch_fast<T, ORDER, RC, 64, true>(a, p, table, s);
-    switch (p.W) {
-      case 128:
-        if (a.mom) return launch_fast<T, ORDER, RC, 128, false, true>(a, p, table, s);
-        return launch_fast<T, ORDER, RC, 128, false>(a, p, table, s);
-      case 64:
-        if (a.mom) return launch_fast<T, ORDER, RC, 64, false, true>(a, p, table, s);
-        return launch_fast<T, ORDER, RC, 64, false>(a, p, table, s);
-      case 48: return launch_fast<T, ORDER, RC, 48, false>(a, p, table, s);
-      case 32: return launch_fast<T, ORDER, RC, 32, false>(a, p, table, s);
-      default: break;
+  if constexpr (RC == 32) {  // strided 128-pencil tiles of 64-cell pencils only
+    if (!p.fast || a.inner == 1 || p.W != 128) return hipErrorInvalidValue;
+    if (a.mom) return launch_fast<T, ORDER, RC, 128, false, true>(a, p, table, s);
+    return launch_fast<T, ORDER, RC, 128, false>(a, p, table, s);
+  } else {
+    if (p.fast) {
+      if (a.inner == 1) return launch_fast<T, ORDER, RC, 64, true>(a, p, table, s);
+      switch (p.W) {
+        case 128:
+          if (a.mom) return launch_fast<T, ORDER, RC, 128, false, true>(a, p, table, s);
+          return launch_fast<T, ORDER, RC, 128, false>(a, p, table, s);
+        case 64:
+          if (a.mom) return launch_fast<T, ORDER, RC, 64, false, true>(a, p, table, s);
+          return launch_fast<T, ORDER, RC, 64, false>(a, p, table, s);
+        case 48: return launch_fast<T, ORDER, RC, 48, false>(a, p, table, s);
+        case 32: return launch_fast<T, ORDER, RC, 32, false>(a, p, table, s);
+        default: break;
+      }
     }
+    return launch_k<T, ORDER, SLMPP_LIM_MPP, RC, 0>(a, p, table, s);
   }
-  return launch_k<T, ORDER, SLMPP_LIM_MPP, RC, 0>(a, p, table, s);
 }
 
 template <typename T, int ORDER, int LIM>
@@ -1254,6 +1260,7 @@ hipError_t launch_r(const SweepArgs& a, const SweepPlan& p, const void* table, h
       case 12: return launch_w<T, ORDER, 12>(a, p, table, s);
       case 16: return launch_w<T, ORDER, 16>(a, p, table, s);
       case 24: return launch_w<T, ORDER, 24>(a, p, table, s);
+      case 32: return launch_w<T, ORDER, 32>(a, p, table, s);
       default: break;
     }
   }
@@ -1414,7 +1421,7 @@ SweepPlan plan_batch_sweep(int dtype, int order, int32_t n, int64_t npen, int64_
 size_t pencil_table_bytes(int dtype, int64_t count) { return entry_bytes(dtype) * (size_t)count; }
 
 SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen, int64_t inner,
-                     int32_t nfast, int W_override, int S_override) {
+                     int32_t nfast, int W_override, int S_override, bool moment) {
   SweepPlan p{};
   const size_t es = dtype == SLMPP_F64 ? 8 : 4;
   const int gh = order == 7 ? 4 : 3;
@@ -1437,10 +1444,17 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
   // `inner` pencils, so W divides inner when a divisor in the list exists.
   // Wider tiles read longer contiguous runs of each row (128 pencils: 512 B
   // in FP32), which the strided x sweeps need; a width is taken only when
-  // some compile-time segment length fits it.
+  // some compile-time segment length fits it.  Segments of 32 cells exist
+  // only for strided 128-pencil tiles of 64-cell pencils, and not with the
+  // row sums of the moment (their registers would halve the occupancy; the
+  // 64-pencil tiles of 16-cell segments are faster there).
+  auto seg_ok = [&](int c, int Wc) {
+    return n % c == 0 && Wc * (n / c) <= 256 &&
+           (c != 32 || (Wc == 128 && n == 64 && !contiguous && !moment));
+  };
   auto has_r = [&](int Wc) {
-    for (int c : {12, 16, 24})
-      if (n % c == 0 && Wc * (n / c) <= 256) return true;
+    for (int c : {12, 16, 24, 32})
+      if (seg_ok(c, Wc)) return true;
     return false;
   };
   int W = 0;
@@ -1473,8 +1487,8 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
     R = (n % S == 0 && (n / S == 12 || n / S == 16 || n / S == 24)) ? n / S : 0;
     p.S = S;
   } else {
-    for (int c : {12, 16, 24}) {
-      if (n % c == 0 && W * (n / c) <= 256) {
+    for (int c : {12, 16, 24, 32}) {
+      if (seg_ok(c, W)) {
         R = c;
         break;
       }
@@ -1497,6 +1511,11 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
   p.fast = R > 0 && R % vn == 0 && fits32 && W_override == 0 &&
            (contiguous ? (W == 64 && n % vn == 0) : (inner % W == 0 && inner % vn == 0 &&
                                                      (W == 128 || W == 64 || W == 48 || W == 32)));
+  if (R == 32 && !p.fast) {  // 32-cell segments exist in the fast kernel only
+    R = 0;
+    p.R = 0;
+    p.lds_bytes = lds(W, false);
+  }
   if (p.fast) p.lds_bytes = lds(W, true);
   return p;
 }

@@ -421,3 +421,43 @@ def test_collapse_small_matches_oracle(S, storage):
     say(f"  L1 rel = {err:.3e}")
     assert err <= (1e-12 if storage == 0 else 1e-5)
     assert diag["nonfinite"] == 0
+
+
+# 64-cell strided axes: 128-pencil tiles with 32 cells per thread
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("order", [5, 7])
+def test_fast_tiles_random_sweeps_64(S, storage, order):
+    """The x1 axis of a 2D2V 64 x 8 x 16^2 grid (64-cell pencils, 2048
+    pencils apart) with random data, shifts up to three cells in both
+    directions and both boundary kinds, against the oracle."""
+    for x_bc in (W.BC_PERIODIC, W.BC_OUTFLOW):
+        spec = W.spec(2, [64, 8], [16, 16], [0.0, 0.0], [1.0, 1.3], [-2.0, -3.0], [2.0, 2.5],
+                      order=order, limiter=W.LIM_MPP, x_bc=x_bc)
+        grid = O.make_grid(spec)
+        f0 = _stored(W.random_field(grid.shape, 6400 + order + 10 * x_bc), storage)
+        for dt in (0.011, -0.029, 0.0007):
+            say(f"case fast64 order={order} storage={storage} bc={x_bc} dt={dt}")
+            ctx = _ctx(S, spec, storage, f0)
+            ref = f0.copy()
+            ctx.advect_x(0, dt)
+            O.advect_x(grid, ref, 0, dt)
+            got = ctx.get_f()
+            ctx.close()
+            tol = 1e-13 if storage == 0 else 64 * 2.0 ** -24
+            assert np.abs(got - ref).max() / np.abs(ref).max() <= tol, (x_bc, dt)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_fast_tiles_64_steps(S, storage):
+    """Two Strang steps on a 2D2V 64 x 8 x 16^2 Landau grid: the x1 sweep
+    takes the 128-pencil, 32-cell tiles with the fused velocity moment."""
+    spec = W.landau_run(2, 64, 16, 0.5, 0.2, 7)
+    spec["nx"] = [64, 8, 1]
+    spec["dt"] *= 3.0
+    say(f"case landau 2d2v 64x8x16^2 storage={storage}")
+    got, ref, diag = _run_pair(S, spec, storage, 2)
+    err = l1rel(got, ref)
+    say(f"  L1 rel = {err:.3e}")
+    assert err <= (1e-13 if storage == 0 else 1e-6)
+    assert diag["nonfinite"] == 0
