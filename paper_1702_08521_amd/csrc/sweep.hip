@@ -1260,7 +1260,9 @@ hipError_t launch_r(const SweepArgs& a, const SweepPlan& p, const void* table, h
       case 12: return launch_w<T, ORDER, 12>(a, p, table, s);
       case 16: return launch_w<T, ORDER, 16>(a, p, table, s);
       case 24: return launch_w<T, ORDER, 24>(a, p, table, s);
-      case 32: return launch_w<T, ORDER, 32>(a, p, table, s);
+      case 32:  // planned for FP32 only
+        if constexpr (sizeof(T) == 4) return launch_w<T, ORDER, 32>(a, p, table, s);
+        return hipErrorInvalidValue;
       default: break;
     }
   }
@@ -1445,12 +1447,13 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
   // Wider tiles read longer contiguous runs of each row (128 pencils: 512 B
   // in FP32), which the strided x sweeps need; a width is taken only when
   // some compile-time segment length fits it.  Segments of 32 cells exist
-  // only for strided 128-pencil tiles of 64-cell pencils, and not with the
-  // row sums of the moment (their registers would halve the occupancy; the
-  // 64-pencil tiles of 16-cell segments are faster there).
+  // only for strided 128-pencil tiles of 64-cell FP32 pencils, and not with
+  // the row sums of the moment: with those, or in FP64, their registers
+  // would halve the occupancy, and 64-pencil tiles of 16-cell segments are
+  // faster.
   auto seg_ok = [&](int c, int Wc) {
     return n % c == 0 && Wc * (n / c) <= 256 &&
-           (c != 32 || (Wc == 128 && n == 64 && !contiguous && !moment));
+           (c != 32 || (Wc == 128 && n == 64 && !contiguous && !moment && es == 4));
   };
   auto has_r = [&](int Wc) {
     for (int c : {12, 16, 24, 32})
