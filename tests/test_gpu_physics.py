@@ -13,6 +13,10 @@ the dispersion relation and the oracle, and FP32 storage against FP64.
   against FP64 on the same GPU, the same three figures.
 * Three-dimensional Landau damping at 24^3 x 24^3 (the benchmark's physics
   at a size the oracle finishes): FP64 and FP32 against the oracle.
+* Spherical collapse (Sec. 3.4) at 32^3 x 24^3 and 48^3 x 32^3: mass,
+  kinetic and potential energy histories against the initial values of a
+  uniform sphere, mass and energy conservation, and the collapse and bounce
+  of the virial ratio around the free-fall time.
 """
 import numpy as np
 import pytest
@@ -219,3 +223,88 @@ def test_c4_landau_3d3v_at_24_vs_oracle(S, storage):
     err = l1rel(got, run.f)
     say(f"  L1 vs oracle {err:.2e}")
     assert err <= (1e-12 if storage == 0 else 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Test-4 (Sec. 3.4): spherical collapse, mass / kinetic / potential histories
+# ---------------------------------------------------------------------------
+def _collapse_history(S, nx, nv, storage, t_end, every):
+    """(t, M, K, W) samples of a collapse run: M from the library's mass
+    diagnostic, K = 1/2 sum_x dx^3 rho (|u|^2 + sum_l sigma_l^2) from its
+    velocity moments, W = 1/2 sum_x dx^3 rho phi from its isolated solve."""
+    import torch
+
+    spec = W.collapse_3d3v(nx=nx, nv=nv, order=5)
+    ctx = _ctx(S, spec, storage)
+    nxs = nx ** 3
+    dx = (spec["x_hi"][0] - spec["x_lo"][0]) / nx
+    dev = dict(dtype=torch.float64, device="cuda")
+    rho, phi = torch.empty(nxs, **dev), torch.empty(nxs, **dev)
+    mean, disp, acc = (torch.empty(3 * nxs, **dev) for _ in range(3))
+
+    def sample(t):
+        ctx.velocity_moments(rho, mean, disp)
+        ctx.poisson_solve(rho, acc, phi)
+        ctx.sync()
+        r = rho.cpu().numpy()
+        u = mean.cpu().numpy().reshape(3, nxs)
+        s2 = disp.cpu().numpy().reshape(3, nxs)
+        K = 0.5 * dx ** 3 * float(np.sum(r * ((u * u).sum(0) + s2.sum(0))))
+        Wp = 0.5 * dx ** 3 * float(np.sum(r * phi.cpu().numpy()))
+        return t, ctx.diag()["mass"], K, Wp
+
+    dt = spec["dt"]
+    hist = [sample(0.0)]
+    nsteps = int(round(t_end / dt))
+    for k in range(every, nsteps + 1, every):
+        ctx.step(dt, every)
+        hist.append(sample(k * dt))
+    ctx.close()
+    return spec, np.array(hist)
+
+
+@pytest.mark.parametrize("storage", [1, 0])
+def test_collapse_energy_history(S, storage):
+    """Uniform sphere of radius a = 2, mass M = 1 (G = 1), Maxwellian of
+    sigma^2 = 0.05 (2K/|W| = 1/2 at the start), 32^3 x 24^3:
+    * K(0) = 3/2 M sigma^2 and W(0) = -3 G M^2 / (5 a) of the sampled sphere;
+    * mass conserved while nothing reaches the edges of the box, and after
+      that only lost (outflow boundaries);
+    * E = K + W within 2% of E(0) up to t = 1 (its drift shrinks with
+      resolution: test_collapse_energy_converges);
+    * the sphere collapses: 2K/|W| rises from 1/2 to a maximum above 1.3
+      after the free-fall time t_ff = sqrt(3 pi / (32 G rho_0)) = pi and
+      before 1.5 t_ff, then falls (the bounce)."""
+    spec, h = _collapse_history(S, 32, 24, storage, 5.0, 8)
+    t, M, K, Wp = h.T
+    sig2, a = spec["sigma2"], spec["radius"]
+    say(f"collapse 32^3x24^3 storage={storage}: M0={M[0]:.6f} K0={K[0]:.6f} W0={Wp[0]:.6f}")
+    for row in h[::4]:
+        say("  t=%.3f M=%.7f K=%.5f W=%.5f 2K/|W|=%.3f" % (row[0], row[1], row[2], row[3],
+                                                           2 * row[2] / abs(row[3])))
+    assert abs(K[0] / (1.5 * M[0] * sig2) - 1.0) <= 1e-4
+    assert abs(Wp[0] / (-3.0 * M[0] ** 2 / (5.0 * a)) - 1.0) <= 1e-2
+    early = t <= 1.0 + 1e-12
+    assert np.max(np.abs(M[early] / M[0] - 1.0)) <= 1e-6
+    assert np.all(np.diff(M) <= 1e-6 * M[0])
+    E = K + Wp
+    assert np.max(np.abs(E[early] / E[0] - 1.0)) <= 0.02
+    q = 2 * K / np.abs(Wp)
+    ip = int(np.argmax(q))
+    say(f"  max 2K/|W| = {q[ip]:.3f} at t = {t[ip]:.3f}")
+    assert q[ip] > 1.3
+    assert np.pi <= t[ip] <= 1.5 * np.pi
+    assert q[-1] < q[ip]
+    assert np.all(np.diff(q[: ip + 1]) > 0)
+
+
+def test_collapse_energy_converges(S):
+    """The energy drift at t = 1 shrinks with resolution: 48^3 x 32^3
+    against 32^3 x 24^3 (FP32 f), at least by the factor 0.6."""
+    drift = []
+    for nx, nv in ((32, 24), (48, 32)):
+        _, h = _collapse_history(S, nx, nv, 1, 1.0, 16)
+        E = h[:, 2] + h[:, 3]
+        drift.append(abs(E[-1] / E[0] - 1.0))
+    say(f"collapse energy drift at t = 1: 32^3 {drift[0]:.4f}, 48^3 {drift[1]:.4f}")
+    assert drift[1] <= 0.6 * drift[0]
