@@ -1,5 +1,6 @@
-"""Test-1 of Sec. 3.1 through the GPU sweeps: the design order on a
-sinusoid and positivity on a quartic sine.
+"""Test-1 of Sec. 3.1 through the GPU sweeps (the design order on a
+sinusoid, positivity on a quartic sine, the rectangle, the split 2D
+sinusoid) and the Poisson accuracy test of App. C through the GPU solve.
 
 A 1D1V grid with one velocity row at speed 1 on x in [0, 1) (periodic):
 every x-sweep advects the profile by nu = 0.2 cells; after t = 1 the exact
@@ -110,3 +111,71 @@ def test_order_on_quartic_sine_with_pp(S, order):
     say(f"Test-1c SL-MPP{order}: slope {slope:.2f}")
     assert min(r[1] for r in res) >= 0.0
     assert slope > GOLD["order_quartic_sine"]["value"] - 0.5
+
+
+def test_rectangle_first_order_no_overshoot(S):
+    """Test-1a (SL-MPP7): bounded by [0, 1] throughout, error ~ first order."""
+    Ns = [32, 64, 128]
+    res = [_gpu_advect(S, "rect", 7, W.LIM_MPP, N) for N in Ns]
+    slope = _slope([r[0] for r in res], Ns)
+    say(f"Test-1a: slope {slope:.2f}, min {min(r[1] for r in res):.3e}, max {max(r[2] for r in res):.6f}")
+    assert all(r[1] >= 0.0 and r[2] <= 1.0 for r in res)
+    assert 0.6 < slope < 1.2
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_two_dimensional_split_order(S, order):
+    """Test-1d: the split 2D sinusoid with velocities (1, 0.5) keeps the 1D
+    order.  A 2D2V grid with one velocity cell per axis (centres 1 and 0.5),
+    x sweeps along x_2 (contiguous) then x_1 (strided by N)."""
+    Ns = [16, 32] if order == 7 else [32, 64]
+    errs = []
+    for N in Ns:
+        spec = W.spec(2, [N, N], [1, 1], [0.0, 0.0], [1.0, 1.0], [0.5, 0.0], [1.5, 1.0],
+                      order=order, limiter=W.LIM_MP, kappa=0.0)
+        x = W.centers(0.0, 1.0, N)
+        X, Y = np.meshgrid(x, x, indexing="ij")
+        f0 = 1.0 + 0.5 * np.sin(2 * np.pi * X) + 0.5 * np.sin(2 * np.pi * Y)
+        ctx = S.Context(S.make_desc(spec, 0))
+        ctx.init_f_host(f0.reshape(N, N, 1, 1))
+        dt = NU / N
+        for _ in range(int(round(1.0 / dt))):
+            ctx.advect_x(1, dt)
+            ctx.advect_x(0, dt)
+        f = ctx.get_f().reshape(N, N)
+        ctx.close()
+        # after t = 1: x_1 moved by one period, x_2 by half of one
+        ref = 1.0 + 0.5 * np.sin(2 * np.pi * X) + 0.5 * np.sin(2 * np.pi * (Y - 0.5))
+        errs.append(np.abs(f - ref).sum() / np.abs(ref).sum())
+    slope = _slope(errs, Ns)
+    say(f"Test-1d order {order}: errors {['%.3e' % e for e in errs]}, slope {slope:.2f}")
+    assert slope == pytest.approx(GOLD["order_2d_sine"]["value"][str(order)], abs=0.35)
+
+
+def test_poisson_orders_app_c(S):
+    """App. C: rho = rho_bar (1 + A sin kx) with 16 waves on the GPU field
+    solve; potential and force converge with orders 2, 4, 6."""
+    import torch
+
+    L, A, G = 1.0, GOLD["poisson_test"]["A"], 1.0
+    k = 2 * np.pi * GOLD["poisson_test"]["waves"] / L
+    for p in GOLD["poisson_orders"]["value"]:
+        ep, ef = [], []
+        Ns = [128, 256, 512]
+        for N in Ns:
+            s = W.spec(1, N, 4, 0.0, L, -1.0, 1.0, kappa=4 * np.pi * G, poisson_order=p)
+            ctx = S.Context(S.make_desc(s, 0))
+            x = W.centers(0.0, L, N)
+            dev = dict(dtype=torch.float64, device="cuda")
+            rho = torch.tensor(1.0 + A * np.sin(k * x), **dev)
+            phi, acc = torch.empty(N, **dev), torch.empty(N, **dev)
+            ctx.poisson_solve(rho, acc, phi)
+            ctx.sync()
+            ph, ac = phi.cpu().numpy(), acc.cpu().numpy()
+            ctx.close()
+            ep.append(np.mean(np.abs(ph + 4 * np.pi * G * A / k ** 2 * np.sin(k * x))))
+            ef.append(np.mean(np.abs(ac - 4 * np.pi * G * A / k * np.cos(k * x))))
+        sp, sf = _slope(ep, Ns), _slope(ef, Ns)
+        say(f"App. C order {p}: potential slope {sp:.2f}, force slope {sf:.2f}")
+        assert sp == pytest.approx(p, abs=0.15)
+        assert sf == pytest.approx(p, abs=0.2)

@@ -13,6 +13,8 @@ the dispersion relation and the oracle, and FP32 storage against FP64.
   against FP64 on the same GPU, the same three figures.
 * Three-dimensional Landau damping at 24^3 x 24^3 (the benchmark's physics
   at a size the oracle finishes): FP64 and FP32 against the oracle.
+* One-dimensional gravitational instability (Sec. 3.2) at 64 x 128: growth
+  and damping rates of the density wave against the dispersion relation.
 * Spherical collapse (Sec. 3.4) at 32^3 x 24^3 and 48^3 x 32^3: mass,
   kinetic and potential energy histories against the initial values of a
   uniform sphere, mass and energy conservation, and the collapse and bounce
@@ -308,3 +310,36 @@ def test_collapse_energy_converges(S):
         drift.append(abs(E[-1] / E[0] - 1.0))
     say(f"collapse energy drift at t = 1: 32^3 {drift[0]:.4f}, 48^3 {drift[1]:.4f}")
     assert drift[1] <= 0.6 * drift[0]
+
+
+# ---------------------------------------------------------------------------
+# Test-2 physics in 1D (Sec. 3.2): gravitational instability
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ratio", [0.5, 1.1])
+def test_jeans_rate_1d(S, ratio):
+    """Growth (k/k_J = 0.5) or damping (1.1) of the density wave at 64 x 128
+    (FP64), against the roots of 1 - (k_J/k)^2 (1 + z Z(z)) = 0 for a unit
+    Maxwellian at k = 2 pi: Im w / k = 1.374404 and -0.148252 (the oracle
+    pins derive both from the dispersion relation)."""
+    k = 2 * np.pi
+    want = (1.374404 if ratio < 1 else -0.148252) * k
+    spec = W.jeans_3d3v(n=64, k_over_kj=ratio, D=1, nv=128)
+    spec["v_lo"][0], spec["v_hi"][0] = -6.0, 6.0
+    spec["dt"] = 0.5 * (1.0 / 64) / 6.0
+    T, lo, hi = (0.45, 0.1, 0.4) if ratio < 1 else (1.6, 0.4, 1.6)
+    ctx = _ctx(S, spec, 0)
+    nx, dt = 64, spec["dt"]
+    n = int(round(T / dt))
+    ts, amp = [], []
+    for it in range(n + 1):
+        _, acc = ctx.get_field()
+        ts.append(it * dt)
+        amp.append(abs(np.fft.fft(acc[:nx])[1]))
+        if it < n:
+            ctx.step(dt, 1)
+    ctx.close()
+    ts, amp = np.array(ts), np.array(amp)
+    sel = (ts > lo) & (ts < hi)
+    rate = np.polyfit(ts[sel], np.log(amp[sel]), 1)[0]
+    say(f"Jeans 1D k/k_J = {ratio}: rate {rate:.4f} against {want:.4f}")
+    assert rate == pytest.approx(want, rel=0.02 if ratio < 1 else 0.1)
