@@ -461,3 +461,36 @@ def test_fast_tiles_64_steps(S, storage):
     say(f"  L1 rel = {err:.3e}")
     assert err <= (1e-13 if storage == 0 else 1e-6)
     assert diag["nonfinite"] == 0
+
+
+# the longest pencils a grid may have (4096 cells per axis)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", [0, 1])
+def test_longest_pencils(S, storage):
+    """A 4096 x 4096 1D1V grid (the axis limit) with random data: one x
+    sweep (pencils strided by 4096) and one v sweep (contiguous pencils),
+    shifts of several cells, against the oracle."""
+    import torch
+
+    n = 4096
+    spec = W.spec(1, [n], [n], [0.0], [1.0], [-2.0], [2.0], order=7, limiter=W.LIM_MPP)
+    grid = O.make_grid(spec)
+    f0 = _stored(W.random_field(grid.shape, 4096), storage)
+    acc = W.random_accel(n, 1, 4097, scale=1.0)
+    hv = 4.0 / n
+    dt = 2.7 * (1.0 / n) / 2.0  # x shifts up to 2.7 cells
+    comp = acc * 3.3 * hv / dt  # v shifts up to ~3.3 cells
+    for axis in (0, 1):
+        say(f"case longest pencils axis={axis} storage={storage}")
+        ctx = _ctx(S, spec, storage, f0)
+        ref = f0.copy()
+        if axis == 0:
+            ctx.advect_x(0, dt)
+            O.advect_x(grid, ref, 0, dt)
+        else:
+            ctx.advect_v(0, dt, torch.tensor(comp, dtype=torch.float64, device="cuda"))
+            O.advect_v(grid, ref, 0, dt, comp)
+        got = ctx.get_f()
+        ctx.close()
+        tol = 1e-13 if storage == 0 else 64 * 2.0 ** -24
+        assert np.abs(got - ref).max() / np.abs(ref).max() <= tol, axis
