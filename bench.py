@@ -349,6 +349,33 @@ def main():
         "detail": {"per_class": per_class, "mass": diag["mass"], "f_min": diag["f_min"],
                    "nonfinite": diag["nonfinite"]},
     }
+    # velocity-space diagnostics of the same f (each one read of f)
+    nxs = int(np.prod(spec["nx"][:D]))
+    nvs = int(np.prod(spec["nv"][:D]))
+    rho_d = torch.empty(nxs, dtype=torch.float64, device=dev)
+    mean_d = torch.empty(D * nxs, dtype=torch.float64, device=dev)
+    disp_d = torch.empty(D * nxs, dtype=torch.float64, device=dev)
+    F_d = torch.empty(nvs, dtype=torch.float64, device=dev)
+    es_f = 4 if storage == slmpp.F32 else 8
+    diag_rates = {}
+    for name, fn in (("density_moment", lambda: ctx.density_moment(rho_d)),
+                     ("velocity_moments", lambda: ctx.velocity_moments(rho_d, mean_d, disp_d)),
+                     ("velocity_distribution", lambda: ctx.velocity_distribution(F_d))):
+        fn()
+        ctx.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        diag_rates[name] = {"ms": round(ms, 3), "GB_s": round(es_f * cells / (ms * 1e-3) / 1e9, 1)}
+    out["detail"]["diagnostics"] = diag_rates
+    log(f"[bench] diagnostics: {diag_rates}")
+    del rho_d, mean_d, disp_d, F_d
+
     if args.fp64_compare > 0 and storage == slmpp.F32:
         # the same workload from the same start with FP64 storage on the same
         # GPU: its rate, and the error of FP32 storage after the same steps

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "slmpp_internal.hpp"
 
@@ -105,8 +106,9 @@ __global__ void __launch_bounds__(NT) moment_kernel(const T* __restrict__ f, int
 // Velocity moments of one spatial cell per workgroup (Sec. 2.3): density,
 // mean velocity and dispersion per velocity axis, two passes over the
 // cell's contiguous velocity block (the second re-reads it from cache).
-template <typename T, int NT>
-__global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restrict__ f, int D,
+template <typename T, int NT, int D>  // D: velocity axes (a constant: the loops over
+                                      // axes unroll and every accumulator stays in registers)
+__global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restrict__ f, int,
                                                               int64_t nvs, int3 nv, double3 vlo,
                                                               double3 dv, double dvol, int64_t nxs,
                                                               double* __restrict__ rho,
@@ -115,18 +117,39 @@ __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restric
   const T* b = f + (int64_t)blockIdx.x * nvs;
   const int n[3] = {nv.x, nv.y, nv.z};
   const double lo[3] = {vlo.x, vlo.y, vlo.z}, h[3] = {dv.x, dv.y, dv.z};
-  auto centres = [&](int64_t k, double* v) {
-    int64_t rem = k;
+  // velocity index of element k as digits (last axis fastest): the digits
+  // of this thread's first element and of the stride NT, then a digit-wise
+  // add with carries per step instead of a division per element
+  int j0[3] = {0, 0, 0}, st[3] = {0, 0, 0};
+  {
+    int64_t rem = threadIdx.x, str = NT;
     for (int l = D - 1; l >= 0; --l) {
-      const int64_t j = rem % n[l];
+      j0[l] = (int)(rem % n[l]);
       rem /= n[l];
-      v[l] = lo[l] + ((double)j + 0.5) * h[l];
+      st[l] = (int)(str % n[l]);
+      str /= n[l];
+    }
+  }
+  int j[3];
+  auto restart = [&]() {
+    for (int l = 0; l < 3; ++l) j[l] = j0[l];
+  };
+  auto centres = [&](double* v) {
+    for (int l = 0; l < D; ++l) v[l] = lo[l] + ((double)j[l] + 0.5) * h[l];
+  };
+  auto next = [&]() {  // j += st; past the last element the digits are unused
+    int carry = 0;
+    for (int l = D - 1; l >= 0; --l) {
+      j[l] += st[l] + carry;
+      carry = j[l] >= n[l];
+      if (carry) j[l] -= n[l];
     }
   };
   KSum s0{0.0, 0.0}, s1[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-  for (int64_t k = threadIdx.x; k < nvs; k += NT) {
+  restart();
+  for (int64_t k = threadIdx.x; k < nvs; k += NT, next()) {
     double v[3];
-    centres(k, v);
+    centres(v);
     const double x = (double)b[k];
     kadd(s0, x);
     for (int l = 0; l < D; ++l) kadd(s1[l], x * v[l]);
@@ -139,9 +162,10 @@ __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restric
     u[l] = m0 != 0.0 ? (t1.s + t1.c) / m0 : 0.0;
   }
   KSum s2[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-  for (int64_t k = threadIdx.x; k < nvs; k += NT) {
+  restart();
+  for (int64_t k = threadIdx.x; k < nvs; k += NT, next()) {
     double v[3];
-    centres(k, v);
+    centres(v);
     const double x = (double)b[k];
     for (int l = 0; l < D; ++l) {
       const double d = v[l] - u[l];
@@ -633,12 +657,25 @@ hipError_t launch_velocity_moments(int dtype, const void* f, int D, const int64_
   const double3 lo3 = make_double3(vlo[0], D > 1 ? vlo[1] : 0.0, D > 2 ? vlo[2] : 0.0);
   const double3 dv3 = make_double3(dv[0], D > 1 ? dv[1] : 1.0, D > 2 ? dv[2] : 1.0);
   constexpr int NT = 256;
-  if (dtype == SLMPP_F64)
-    hipLaunchKernelGGL((velocity_moments_kernel<double, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
-                       (const double*)f, D, nvs, n3, lo3, dv3, dvol, nxs, rho, mean, disp);
-  else
-    hipLaunchKernelGGL((velocity_moments_kernel<float, NT>), dim3((unsigned)nxs), dim3(NT), 0, s,
-                       (const float*)f, D, nvs, n3, lo3, dv3, dvol, nxs, rho, mean, disp);
+  if (D < 1 || D > 3) return hipErrorInvalidValue;
+  auto go = [&](auto tag, auto axes) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((velocity_moments_kernel<T, NT, decltype(axes)::value>), dim3((unsigned)nxs),
+                       dim3(NT), 0, s, (const T*)f, D, nvs, n3, lo3, dv3, dvol, nxs, rho, mean,
+                       disp);
+  };
+  using A1 = std::integral_constant<int, 1>;
+  using A2 = std::integral_constant<int, 2>;
+  using A3 = std::integral_constant<int, 3>;
+  if (dtype == SLMPP_F64) {
+    if (D == 1) go(0.0, A1{});
+    if (D == 2) go(0.0, A2{});
+    if (D == 3) go(0.0, A3{});
+  } else {
+    if (D == 1) go(0.0f, A1{});
+    if (D == 2) go(0.0f, A2{});
+    if (D == 3) go(0.0f, A3{});
+  }
   return hipGetLastError();
 }
 
