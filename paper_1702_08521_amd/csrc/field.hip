@@ -182,17 +182,32 @@ __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restric
   if (threadIdx.x == 0) rho[blockIdx.x] = dvol * m0;
 }
 
-// F[k] = xvol * sum_x f[x][k]: one thread per velocity cell, rows in x order
+// F[k] = xvol * sum_x f[x][k]: one thread per velocity cell.  Few threads
+// walk long columns here (one per velocity cell), so each keeps 16 loads in
+// flight: rows x = 16 m + r go to accumulator r % 4, merged in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(256) velocity_distribution_kernel(const T* __restrict__ f,
                                                                     int64_t nxs, int64_t nvs,
                                                                     double xvol,
                                                                     double* __restrict__ F) {
+  constexpr int U = 16;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvs;
        k += (int64_t)gridDim.x * blockDim.x) {
-    KSum a{0.0, 0.0};
-    for (int64_t ix = 0; ix < nxs; ++ix) kadd(a, (double)f[ix * nvs + k]);
-    F[k] = xvol * (a.s + a.c);
+    KSum a[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    const T* col = f + k;
+    int64_t ix = 0;
+    for (; ix + U <= nxs; ix += U) {
+      T x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = col[(ix + u) * nvs];
+#pragma unroll
+      for (int u = 0; u < U; ++u) kadd(a[u % 4], (double)x[u]);
+    }
+    for (; ix < nxs; ++ix) kadd(a[0], (double)col[ix * nvs]);
+    kmerge(a[0], a[1]);
+    kmerge(a[2], a[3]);
+    kmerge(a[0], a[2]);
+    F[k] = xvol * (a[0].s + a[0].c);
   }
 }
 
