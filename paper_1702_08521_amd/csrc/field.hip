@@ -105,7 +105,8 @@ __global__ void __launch_bounds__(NT) moment_kernel(const T* __restrict__ f, int
 
 // Velocity moments of one spatial cell per workgroup (Sec. 2.3): density,
 // mean velocity and dispersion per velocity axis, two passes over the
-// cell's contiguous velocity block (the second re-reads it from cache).
+// cell's contiguous velocity block (the second re-reads it from cache);
+// compensated double sums of plain sums over groups of eight elements.
 template <typename T, int NT, int D>  // D: velocity axes (a constant: the loops over
                                       // axes unroll and every accumulator stays in registers)
 __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restrict__ f, int,
@@ -145,15 +146,29 @@ __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restric
       if (carry) j[l] -= n[l];
     }
   };
+  // each thread adds groups of up to kGroup of its elements plainly and
+  // feeds the group sums to the compensated accumulators
+  constexpr int kGroup = 8;
   KSum s0{0.0, 0.0}, s1[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  double p0 = 0.0, p1[3] = {0.0, 0.0, 0.0};
+  int cnt = 0;
   restart();
   for (int64_t k = threadIdx.x; k < nvs; k += NT, next()) {
     double v[3];
     centres(v);
     const double x = (double)b[k];
-    kadd(s0, x);
-    for (int l = 0; l < D; ++l) kadd(s1[l], x * v[l]);
+    p0 += x;
+    for (int l = 0; l < D; ++l) p1[l] += x * v[l];
+    if (++cnt == kGroup) {
+      kadd(s0, p0);
+      for (int l = 0; l < D; ++l) kadd(s1[l], p1[l]);
+      p0 = 0.0;
+      for (int l = 0; l < D; ++l) p1[l] = 0.0;
+      cnt = 0;
+    }
   }
+  kadd(s0, p0);
+  for (int l = 0; l < D; ++l) kadd(s1[l], p1[l]);
   const KSum t0 = block_ksum<NT>(s0);
   const double m0 = t0.s + t0.c;
   double u[3] = {0.0, 0.0, 0.0};
@@ -162,6 +177,8 @@ __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restric
     u[l] = m0 != 0.0 ? (t1.s + t1.c) / m0 : 0.0;
   }
   KSum s2[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  double p2[3] = {0.0, 0.0, 0.0};
+  cnt = 0;
   restart();
   for (int64_t k = threadIdx.x; k < nvs; k += NT, next()) {
     double v[3];
@@ -169,9 +186,17 @@ __global__ void __launch_bounds__(NT) velocity_moments_kernel(const T* __restric
     const double x = (double)b[k];
     for (int l = 0; l < D; ++l) {
       const double d = v[l] - u[l];
-      kadd(s2[l], x * d * d);
+      p2[l] += x * d * d;
+    }
+    if (++cnt == kGroup) {
+      for (int l = 0; l < D; ++l) {
+        kadd(s2[l], p2[l]);
+        p2[l] = 0.0;
+      }
+      cnt = 0;
     }
   }
+  for (int l = 0; l < D; ++l) kadd(s2[l], p2[l]);
   for (int l = 0; l < D; ++l) {
     const KSum t2 = block_ksum<NT>(s2[l]);
     if (threadIdx.x == 0) {
