@@ -170,56 +170,74 @@ __global__ void __launch_bounds__(256) batch_poisson_kernel(const BatchRun* __re
   const BatchRun& r = runs[blockIdx.x];
   const int D = r.D;
   const int total = (int)r.nxs;
+  // per-axis values in arrays indexed by constants only (the loops over
+  // axes run to 3 with a guard and unroll), so that they stay in registers
   int nx[3] = {1, 1, 1}, inner[3] = {1, 1, 1}, toff[3] = {0, 0, 0};
   int ntw = 0;
-  for (int l = 0; l < D; ++l) {
-    nx[l] = (int)r.nx[l];
-    toff[l] = ntw;
-    ntw += nx[l];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l < D) {
+      nx[l] = (int)r.nx[l];
+      toff[l] = ntw;
+      ntw += nx[l];
+    }
   }
-  for (int l = D - 2; l >= 0; --l) inner[l] = inner[l + 1] * nx[l + 1];
+#pragma unroll
+  for (int l = 1; l >= 0; --l)
+    if (l <= D - 2) inner[l] = inner[l + 1] * nx[l + 1];
   double2* A = reinterpret_cast<double2*>(smem);
   double2* B = A + total;
   double2* tw = B + total;  // roots of unity of axis l at tw + toff[l]
   double* sym = reinterpret_cast<double*>(tw + ntw);  // symbol of axis l at sym + toff[l]
   for (int t = threadIdx.x; t < ntw; t += blockDim.x) {
     int l = 0;
-    while (l + 1 < D && t >= toff[l + 1]) ++l;
-    const int k = t - toff[l];
+    if (1 < D && t >= toff[1]) l = 1;
+    if (2 < D && t >= toff[2]) l = 2;
+    const int k = t - (l == 0 ? toff[0] : (l == 1 ? toff[1] : toff[2]));
+    const int n = l == 0 ? nx[0] : (l == 1 ? nx[1] : nx[2]);
     double sn, cs;
-    sincospi(2.0 * (double)k / (double)nx[l], &sn, &cs);
+    sincospi(2.0 * (double)k / (double)n, &sn, &cs);
     tw[t] = make_double2(cs, sn);
-    sym[t] = lap_symbol(2.0 * M_PI * (double)k / (double)nx[l], r.poisson_order) / (r.h[l] * r.h[l]);
+    sym[t] = lap_symbol(2.0 * M_PI * (double)k / (double)n, r.poisson_order) / (r.h[l] * r.h[l]);
   }
   for (int t = threadIdx.x; t < total; t += blockDim.x) A[t] = make_double2(r.rho[t], 0.0);
   __syncthreads();
   double2* cur = A;
   double2* oth = B;
-  for (int l = 0; l < D; ++l) {
-    lds_dft(cur, oth, tw + toff[l], inner[l], nx[l], -1, total);
-    __syncthreads();
-    double2* tmp = cur;
-    cur = oth;
-    oth = tmp;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l < D) {
+      lds_dft(cur, oth, tw + toff[l], inner[l], nx[l], -1, total);
+      __syncthreads();
+      double2* tmp = cur;
+      cur = oth;
+      oth = tmp;
+    }
   }
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     double L = 0.0;
     bool zero = true;
-    for (int l = 0; l < D; ++l) {
-      const int k = (t / inner[l]) % nx[l];
-      if (k) zero = false;
-      L += sym[toff[l] + k];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      if (l < D) {
+        const int k = (t / inner[l]) % nx[l];
+        if (k) zero = false;
+        L += sym[toff[l] + k];
+      }
     }
     const double g = zero ? 0.0 : r.kappa / L;
     cur[t] = make_double2(cur[t].x * g, cur[t].y * g);
   }
   __syncthreads();
-  for (int l = 0; l < D; ++l) {
-    lds_dft(cur, oth, tw + toff[l], inner[l], nx[l], +1, total);
-    __syncthreads();
-    double2* tmp = cur;
-    cur = oth;
-    oth = tmp;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l < D) {
+      lds_dft(cur, oth, tw + toff[l], inner[l], nx[l], +1, total);
+      __syncthreads();
+      double2* tmp = cur;
+      cur = oth;
+      oth = tmp;
+    }
   }
   // phi into the other buffer's real parts, then the force
   double* phi = reinterpret_cast<double*>(oth);
@@ -229,7 +247,9 @@ __global__ void __launch_bounds__(256) batch_poisson_kernel(const BatchRun* __re
     r.phi[t] = v;
   }
   __syncthreads();
-  for (int l = 0; l < D; ++l) {
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l >= D) break;
     const int n = nx[l], in = inner[l];
     const double h = r.h[l];
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
