@@ -288,3 +288,39 @@ def test_batch_error_paths(S):
     assert e.value.status == S.ERR_INVALID
     assert b.tile_width(0, 2) == 0  # a 1D1V run has axes 0 and 1
     b.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_batch_ensemble_shaped_2d2v_members(S, storage):
+    """2D2V runs shaped like the 256-run ensemble's members (64^2 velocity
+    planes, 32-cell x_1 pencils) but 32 x 4 in space, SL-MPP5 and SL-MPP7,
+    two runs per order, plus one 1D1V run.  With every eligible sweep
+    grouped, the x_1 sweeps take the persistent kernel's 128-pencil tiles of
+    16 cells with the fused moment and the kicks the two-axis pass over the
+    64^2 planes, at both orders; with none grouped, the tile launch.  Both
+    against the oracle for three steps."""
+    specs = []
+    for order in (5, 7):
+        for k, a in ((0.35, 0.05), (0.55, 0.3)):
+            s = W.landau_run(2, 32, 64, k, a, order)
+            s["nx"] = [32, 4, 1]
+            specs.append(s)
+    specs.append(W.landau_1d1v(nx=32, nv=64, order=7))
+    nsteps = 3
+    refs = _oracle_runs(specs, storage, nsteps)
+    tol = 1e-12 if storage == 0 else 1e-5
+    for min_cells in (1, -1):
+        say(f"case batch ensemble-shaped 2d2v storage={storage} min_cells={min_cells}")
+        b = _batch(S, specs, storage)
+        b.set_fast_min_cells(min_cells)
+        if min_cells == 1:
+            for r in range(4):
+                assert b.tile_width(r, 0) == 128, (r, b.tile_width(r, 0))
+                assert b.tile_width(r, 2) == b.tile_width(r, 3) == 64, r
+        b.step(nsteps)
+        for r, (s, ref) in enumerate(zip(specs, refs)):
+            got = b.get_f(r)
+            err = l1rel(got, ref)
+            say(f"  run {r} D={s['D']} order={s['order']}: L1 rel {err:.3e}")
+            assert err <= tol, (min_cells, r, err)
+        b.close()

@@ -53,6 +53,7 @@ CASES = [
     (2, [6, 5], [24, 24], 7),
     (2, [4, 4], [48, 48], 7),
     (2, [4, 3], [64, 64], 5),
+    (2, [4, 3], [64, 64], 7),
     (3, [4, 3, 4], [8, 24, 24], 5),
     (3, [3, 3, 2], [6, 32, 32], 7),
     (3, [2, 2, 2], [5, 48, 48], 5),

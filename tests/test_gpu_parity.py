@@ -498,3 +498,116 @@ def test_longest_pencils(S, storage):
         ctx.close()
         tol = 1e-13 if storage == 0 else 64 * 2.0 ** -24
         assert np.abs(got - ref).max() / np.abs(ref).max() <= tol, axis
+
+
+# ---------------------------------------------------------------------------
+# diagnostics of the field (Sec. 3.3 E-field history, Sec. 3.4 energies)
+# ---------------------------------------------------------------------------
+DIAG_GRIDS = [
+    dict(D=1, nx=[37], nv=[20]),
+    dict(D=2, nx=[9, 6], nv=[8, 10]),
+    dict(D=3, nx=[5, 4, 6], nv=[6, 5, 4]),
+    dict(D=2, nx=[7, 1], nv=[6, 6]),
+]
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("gi", range(len(DIAG_GRIDS)))
+def test_diag_field_energy_and_mode_amplitude(S, gi, storage):
+    """slmpp_diag's field_energy = 1/2 sum_l sum_x a_l(x)^2 dx^D and
+    mode_amp = |sum_x a_1(x) exp(-2 pi i j_1 / nx_1)| / prod(nx), j_1 the
+    x_1 cell index (the cell-centre phase only rotates the sum): against
+    these formulas on the library's own acceleration to 1e-13, and on the
+    oracle's field of the same f to 1e-12 (the field parity bar)."""
+    g = DIAG_GRIDS[gi]
+    D = g["D"]
+    spec = _spec(g, 5, W.LIM_MPP)
+    spec["kappa"] = -1.0 if gi % 2 == 0 else 4 * math.pi
+    grid = O.make_grid(spec)
+    f0 = _stored(W.random_field(grid.shape, 900 + gi), storage)
+    say(f"case diag field energy grid={gi} storage={storage}")
+    ctx = _ctx(S, spec, storage, f0)
+    ctx.field()
+    _, acc = ctx.get_field()
+    d = ctx.diag()
+    ctx.close()
+    nx = g["nx"]
+    nxs = int(np.prod(nx))
+    dxv = float(np.prod([(spec["x_hi"][l] - spec["x_lo"][l]) / nx[l] for l in range(D)]))
+
+    def energy_mode(a):
+        e = 0.5 * float(np.sum(a * a)) * dxv
+        a1 = a[:nxs].reshape(nx[0], -1).sum(axis=1)
+        ph = np.exp(-2j * math.pi * np.arange(nx[0]) / nx[0])
+        return e, abs(np.sum(a1 * ph)) / nxs
+
+    e_own, m_own = energy_mode(acc)
+    assert d["field_energy"] == pytest.approx(e_own, rel=1e-13)
+    assert abs(d["mode_amp"] - m_own) <= 1e-13 * max(m_own, np.abs(acc[:nxs]).max())
+    e_o, m_o = energy_mode(O.field(grid, f0))
+    say(f"  energy {d['field_energy']:.6e} (oracle {e_o:.6e}), |E_1| {d['mode_amp']:.6e} "
+        f"(oracle {m_o:.6e})")
+    assert d["field_energy"] == pytest.approx(e_o, rel=1e-12)
+    assert abs(d["mode_amp"] - m_o) <= 1e-12 * max(m_o, np.abs(acc[:nxs]).max())
+    assert m_o > 1e-6 * np.abs(acc[:nxs]).max() or nx[0] == 1
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_velocity_moments_large_ragged_blocks(S, storage):
+    """Velocity blocks of more than 2048 cells with ragged axes (the moment
+    kernel's index walk across block rows and its flush of eight-element
+    group sums) on random, non-symmetric f, against the oracle."""
+    import torch
+
+    for gi, g in enumerate([dict(D=3, nx=[2, 3, 1], nv=[13, 11, 17]),
+                            dict(D=2, nx=[3, 2], nv=[48, 45]),
+                            dict(D=1, nx=[3], nv=[4093])]):
+        spec = _spec(g, 5, W.LIM_MPP)
+        grid = O.make_grid(spec)
+        f0 = _stored(W.random_field(grid.shape, 60 + gi), storage)
+        say(f"case velocity moments large blocks {g['nv']} storage={storage}")
+        ctx = _ctx(S, spec, storage, f0)
+        D = g["D"]
+        nxs = int(np.prod(g["nx"]))
+        nvs = int(np.prod(g["nv"]))
+        rho = torch.empty(nxs, dtype=torch.float64, device="cuda")
+        mean = torch.empty(D * nxs, dtype=torch.float64, device="cuda")
+        disp = torch.empty(D * nxs, dtype=torch.float64, device="cuda")
+        F = torch.empty(nvs, dtype=torch.float64, device="cuda")
+        ctx.velocity_moments(rho, mean, disp)
+        ctx.velocity_distribution(F)
+        ctx.sync()
+        ctx.close()
+        r_o, m_o, d_o = O.velocity_moments(grid, f0)
+        F_o = O.velocity_distribution(grid, f0)
+        assert np.abs(rho.cpu().numpy() - r_o).max() <= 1e-14 * np.abs(r_o).max()
+        assert np.abs(mean.cpu().numpy() - m_o).max() <= 1e-13 * max(np.abs(m_o).max(), 1.0)
+        assert np.abs(disp.cpu().numpy() - d_o).max() <= 1e-13 * np.abs(d_o).max()
+        assert np.abs(F.cpu().numpy() - F_o).max() <= 1e-14 * np.abs(F_o).max()
+
+
+# the 2D2V members of the 256-run ensemble: 32^2 x 64^2, SL-MPP7
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", [0, 1])
+def test_ensemble_member_2d2v_32x64_order7(S, storage):
+    """Two Strang steps of one 2D2V ensemble member at its full size (the
+    x_1 sweep: 128-pencil tiles of 16 cells with the fused moment; the kicks:
+    the two-axis pass over 64^2 planes), against the oracle."""
+    spec = W.landau_run(2, 32, 64, 0.45, 0.2, 7)
+    say(f"case 2d2v 32^2 x 64^2 order 7 storage={storage}")
+    ctx = _ctx(S, spec, storage)
+    ctx.timing_enable(True)
+    ctx.step(spec["dt"], 2)
+    tim = ctx.timing_read()
+    got = ctx.get_f()
+    ctx.close()
+    assert tim["kick_plane"]["launches"] == 4 and tim["sweep_x1_moment"]["launches"] == 2
+    f0 = None
+    if storage == 1:
+        s, gv = W.separable_factors(spec)
+        f0 = _stored(O.init_separable(O.make_grid(spec), s, gv), 1)
+    run = O.Run(spec, f0)
+    run.step(spec["dt"], 2)
+    err = l1rel(got, run.f)
+    say(f"  L1 rel = {err:.3e}")
+    assert err <= (1e-12 if storage == 0 else 1e-5)

@@ -20,6 +20,9 @@ the dispersion relation and the oracle, and FP32 storage against FP64.
   uniform sphere, mass and energy conservation, and the collapse and bounce
   of the virial ratio around the free-fall time.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -27,6 +30,9 @@ import oracle as O
 from paper_1702_08521_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+SELF_DIV = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "c2_self_divergence.json")))
 
 
 @pytest.fixture(scope="module")
@@ -137,9 +143,12 @@ def test_c2_2000_steps_fp64_vs_oracle_and_fp32_vs_fp64(S, which):
     """FP64 matches the oracle to 1e-12 through the linear phase (step 200).
     Later the two-stream instability and the trapped-particle vortex amplify
     the rounding-order differences between the two (fused multiply-adds,
-    FIR weights against Horner rows): the figure at step 2000 is reported
-    and bounded loosely.  Positivity holds to rounding (f_min >= -1e-14 max f
-    in FP64, -1e-6 max f in FP32) and mass is conserved to rounding."""
+    FIR weights against Horner rows).  The oracle does the same to itself:
+    tests/golden/c2_self_divergence.json holds the L1 difference between two
+    oracle runs whose f0 differ by one ulp per cell (written by the script
+    beside it), and the bound at step 2000 is ten times that figure.
+    Positivity holds to rounding (f_min >= -1e-14 max f in FP64, -1e-6 max f
+    in FP32) and mass is conserved to rounding."""
     spec = W.landau_nl_1d1v() if which == "landau_nl" else W.twostream_1d1v()
     n = 2000
     say(f"case C2 {which} 256 x 512 SL-MPP7 CFL 3, {n} steps")
@@ -161,7 +170,9 @@ def test_c2_2000_steps_fp64_vs_oracle_and_fp32_vs_fp64(S, which):
         f"L1 {l1_32:.2e}, mass drift {drift32:.2e} (FP64 {drift64:.2e}), max field-energy "
         f"deviation {dev_e:.2e}; f_min FP32 {m32_1['f_min']:.2e} of max {m32_1['f_max']:.2e}")
     assert l1_200 <= 1e-12
-    assert l1_64 <= 1e-3
+    selfdiv = SELF_DIV["workloads"][spec["name"]]["l1_rel_by_step"][str(n)]
+    say(f"  oracle self-divergence from one ulp at step {n}: {selfdiv:.2e}")
+    assert l1_64 <= 10.0 * selfdiv
     assert l1_32 <= 1e-3
     assert drift64 <= 1e-12 and drift32 <= 1e-6
     assert dev_e <= 1e-3

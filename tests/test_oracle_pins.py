@@ -239,6 +239,64 @@ def test_periodic_sweep_conserves_mass(oracle):
 
 
 # ---------------------------------------------------------------------------
+# the half-integer tie of the departure split (reading R1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("order", [5, 7])
+def test_half_integer_tie_is_the_limit_from_above(oracle, order):
+    """N = floor(xi + 1/2) jumps at xi = k + 1/2: below the tie the pencil
+    is shifted by k and moved by zeta -> +1/2 with the flux of each face
+    taken from its left (upwind) cell, above it shifted by k + 1 and moved
+    back by zeta -> -1/2 with the mirrored construction.  Without limiters
+    both sides give the same cell values (each new cell is the average over
+    half of two old cells, and at zeta = 1/2 the odd-width primitive
+    stencils are centred on those cells either way), so the unlimited sweep
+    is continuous there.  The MP constraint and the PP limiter act on the
+    upwind cell of each face, which differs between the two sides: that is
+    the scheme's one discontinuity in xi.  Ties go up (zeta = -1/2), so the
+    sweep at an exact tie equals the limit from above (within O(eps) of the
+    sweep at xi + eps, every limiter being continuous in zeta) and, with a
+    limiter, differs by O(1) from the sweep at xi - eps on random data."""
+    g = W.random_field(40, seed=31)
+    scale = np.abs(g).max()
+    eps = 2.0 ** -36
+    for lim in (W.LIM_NONE, W.LIM_MP, W.LIM_MPP):
+        for bc in (W.BC_PERIODIC, W.BC_OUTFLOW):
+            for k in (-4, -2, -1, 0, 1, 3):
+                xi = k + 0.5
+                kw = dict(order=order, limiter=lim, bc=bc)
+                tie = oracle.sweep_pencil(g, xi, **kw)
+                above = oracle.sweep_pencil(g, xi + eps, **kw)
+                below = oracle.sweep_pencil(g, xi - eps, **kw)
+                assert np.abs(tie - above).max() <= 1e-9 * scale, (lim, bc, k)
+                if lim == W.LIM_NONE:
+                    assert np.abs(tie - below).max() <= 1e-9 * scale, (lim, bc, k)
+                else:
+                    assert np.abs(tie - below).max() >= 1e-3 * scale, (lim, bc, k)
+
+
+@pytest.mark.parametrize("order,degree", [(5, 4), (7, 6)])
+def test_half_integer_tie_transports_polynomials_exactly(oracle, order, degree):
+    """At xi = k + 1/2 (shift k + 1, mirrored flux with zeta = 1/2) the
+    unlimited sweep moves cell averages of a polynomial of degree <=
+    order - 1 exactly: each interior cell gets the average of the
+    polynomial over the cell moved back by k + 1/2 cells (CSL identity of
+    Sec. 2.1.2)."""
+    n = 48
+    rng = np.random.default_rng(77 + order)
+    coef = rng.normal(size=degree + 1) / float(n) ** np.arange(degree + 1)
+    j = np.arange(n)
+    g = _poly_cell_averages(coef, j)
+    for k in (-3, -1, 0, 2):
+        xi = k + 0.5
+        out = oracle.sweep_pencil(g, xi, order=order, limiter=W.LIM_NONE, bc=W.BC_OUTFLOW)
+        want = _poly_cell_averages(coef, j - xi)
+        # cells whose stencil after the shift stays inside the pencil
+        m = 6 + abs(k)
+        inside = slice(m, n - m)
+        assert np.abs(out[inside] - want[inside]).max() <= 1e-12 * np.abs(want).max(), k
+
+
+# ---------------------------------------------------------------------------
 # accuracy of Test-1 (Sec. 3.1)
 # ---------------------------------------------------------------------------
 def _advect_error(oracle, profile, order, lim, N, t=1.0, nu=0.2):
@@ -491,6 +549,38 @@ def test_mass_conserved_with_periodic_velocity(oracle):
     m0 = oracle.mass(run.grid, run.f)
     run.step(s["dt"] * 3.0, 100)  # x-CFL 1.5 exercises the shift path
     assert abs(oracle.mass(run.grid, run.f) - m0) <= 1e-14 * 100 * abs(m0)
+
+
+def test_mass_is_the_phase_space_integral(oracle):
+    """oracle_mass = dx^D dv^D sum f, pinned by its absolute value.  f is a
+    product over axes of (1 + 0.3 cos(2 pi x_l / L_l)) and a unit Gaussian
+    centred inside [v_lo, v_hi] at least ten thermal speeds from either end,
+    sampled at cell centres with dv = 1/2.  Its phase-space integral is
+    prod_l L_l: the midpoint sum of the cosine over a whole period vanishes
+    (discrete orthogonality) and that of the Gaussian equals one to far below
+    rounding (the Poisson-summation error exp(-2 pi^2 / dv^2) ~ 1e-34, the
+    tails beyond ten speeds ~ 1e-23).  Unequal axes in 1D, 2D and 3D catch a
+    wrong or swapped volume factor."""
+    cases = [
+        (1, [32], [48], [4 * math.pi], [(-12.0, 12.0)], [0.0]),
+        (2, [12, 10], [44, 48], [2 * math.pi, 3.0], [(-10.0, 12.0), (-13.0, 11.0)], [1.0, -1.0]),
+        (3, [6, 5, 4], [40, 42, 44], [1.0, 2.5, 4.0], [(-10.0, 10.0), (-11.0, 10.0), (-10.0, 12.0)],
+         [0.0, -0.5, 1.0]),
+    ]
+    for D, nx, nv, L, vr, u in cases:
+        s = W.spec(D, nx, nv, [0.0] * D, L, [a for a, _ in vr], [b for _, b in vr])
+        g = oracle.make_grid(s)
+        f = np.ones(())
+        for l in range(D):
+            x = W.centers(0.0, L[l], nx[l])
+            f = np.multiply.outer(f, 1.0 + 0.3 * np.cos(2 * math.pi * x / L[l]))
+        for l in range(D):
+            v = W.centers(vr[l][0], vr[l][1], nv[l])
+            f = np.multiply.outer(f, np.exp(-0.5 * (v - u[l]) ** 2) / math.sqrt(2 * math.pi))
+        f = np.ascontiguousarray(f)
+        assert f.shape == g.shape
+        want = float(np.prod(L))
+        assert oracle.mass(g, f) == pytest.approx(want, rel=1e-13), D
 
 
 def test_separability_2d2v_equals_1d1v(oracle):
