@@ -86,13 +86,37 @@ size_t pencil_table_bytes(int dtype, int64_t count);
 // run) with tmulti holding the v_{D-1} tables of the runs, then their v_D
 // tables; planes and tiles as for one run, times the number of runs for
 // tiles.
+// n / d for 32-bit n by an invariant 32-bit divisor d >= 1 (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994):
+// t = mulhi(m, n), n / d = (t + ((n - t) >> s1)) >> s2 with
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0).  m == 0 marks "not set up".
+struct FastDiv32 {
+  uint32_t m, s1, s2, pad;
+  static FastDiv32 of(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+    FastDiv32 f{};
+    f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+  }
+  __host__ __device__ uint32_t div(uint32_t n) const {
+    const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
 struct PlanePlan {
   int32_t N, PB;       // plane side, planes per tile
   int32_t G, pitch;    // ring of zero cells around each plane in LDS, LDS row
                        // pitch (fixed by order and N; shifts beyond the ring
                        // minus the stencil take bounds-checked reads)
-  int32_t plane_lds;   // LDS elements per plane
+  int32_t plane_lds;   // LDS elements from one plane to the next
+  int32_t uni;         // the planes of a tile share one spatial cell (vouter % PB == 0)
   int64_t planes, vouter, tiles;
+  FastDiv32 vdiv;      // plane -> spatial cell (plane / vouter) while planes < 2^32
   size_t lds_bytes;    // 0: the shape is not supported
 };
 PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t planes,

@@ -43,11 +43,13 @@ template <typename T>
 struct alignas(16) PencilEntry {
   T w[7];        // FIR weights of the CSL flux at |zeta| (first ORDER used)
   T z;           // |zeta|
+  T tz;          // 2 |zeta| (exact), the factor of the PP half-updates
   int32_t base;  // physical row read at processing position 0
-  int32_t dir;   // +1 forward, -1 mirrored (zeta < 0)
-  int32_t absN;  // |N| after periodic reduction
-  int32_t pad;
+  int16_t dir;   // +1 forward, -1 mirrored (zeta < 0)
+  int16_t absN;  // |N| after periodic reduction (at most n + 64 <= 4160)
 };
+static_assert(sizeof(PencilEntry<float>) == 48 && sizeof(PencilEntry<double>) == 80,
+              "pencil entries are 16-byte multiples");
 
 // CSL flux as an FIR filter: Phi_{i-1/2} = sum_k w_k(zeta) f_{i-h+k} with
 // h = 3 (fifth order) or 4 (seventh order), w_k(zeta) = sum_j K[k][j] zeta^j.
@@ -135,18 +137,22 @@ __device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T u_plus, T u_minu
 }
 
 // App. A steps 4-7: the bounds f^min, f^max from the curvatures and the
-// median of the flux with them.
+// median of the flux with them.  The curvatures d_j = f_{j-1} + f_{j+1} -
+// 2 f_j are formed as differences of the one-cell differences
+// dll = f_{i-1} - f_{i-2}, dl = f_i - f_{i-1}, dr = f_{i+1} - f_i and
+// drr = f_{i+2} - f_{i+1}, of which the face already holds dl and dr (and
+// the previous face dll), so that nothing of these steps is computed
+// outside the rare branch that needs them.
 template <typename T>
-__device__ __forceinline__ T mp_clamp(T phi, T fm2, T fm1, T f0, T fp1, T fp2, T alpha) {
-  const T slope = f0 - fm1;
-  const T dm1 = vfma(T(-2), fm1, fm2 + f0);
-  const T d0 = vfma(T(-2), f0, fm1 + fp1);
-  const T dp1 = vfma(T(-2), fp1, f0 + fp2);
+__device__ __forceinline__ T mp_clamp(T phi, T dll, T dl, T dr, T drr, T f0, T fp1, T alpha) {
+  const T dm1 = dl - dll;
+  const T d0 = dr - dl;
+  const T dp1 = drr - dr;
   const T dm4_plus = minmod4(vfma(T(4), d0, -dp1), vfma(T(4), dp1, -d0), d0, dp1);
   const T dm4_minus = minmod4(vfma(T(4), dm1, -d0), vfma(T(4), d0, -dm1), dm1, d0);
-  const T f_ul = vfma(alpha, slope, f0);
-  const T f_md = vfma(T(-0.5), dm4_plus, T(0.5) * (f0 + fp1));
-  const T f_lc = vfma(T(4.0 / 3.0), dm4_minus, vfma(T(0.5), slope, f0));
+  const T f_ul = vfma(alpha, dl, f0);
+  const T f_md = vfma(T(-0.5), dm4_plus, vfma(T(0.5), dr, f0));
+  const T f_lc = vfma(T(4.0 / 3.0), dm4_minus, vfma(T(0.5), dl, f0));
   const T lo = vmax(min3(f0, fp1, f_md), min3(f0, f_ul, f_lc));
   const T hi = vmin(max3(f0, fp1, f_md), max3(f0, f_ul, f_lc));
   return med3(phi, lo, hi);
@@ -166,20 +172,25 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha) {
     return phi;
   } else {
     const T fm2 = q[o], fm1 = q[o + 1], f0 = q[o + 2], fp1 = q[o + 3], fp2 = q[o + 4];
-    const T slope = f0 - fm1;
+    const T dl = f0 - fm1, dr = fp1 - f0;
     // App. A steps 2-3.  The flux is kept when it lies between f_i and f*:
     // that closed interval always lies within [f^min, f^max] of steps 4-6
     // (f* is f_i, f_{i+1} <= f^UL or f^UL, each inside both bounds), so
     // step 7 would return the flux unchanged there.  The strict test of the
     // text only sends the end points (a flux equal to f_i, as in regions of
     // zeros) through steps 4-7.
-    const T fstar = f0 + minmod2(fp1 - f0, alpha * slope);
+    const T fstar = f0 + minmod2(dr, alpha * dl);
     const bool accept = med3(phi, f0, fstar) == phi;
     T phib = phi;
     // steps 4-7, skipped when every lane of the wavefront accepted (the
     // common case on smooth data)
     if (!__all(accept)) {
-      const T c = mp_clamp(phi, fm2, fm1, f0, fp1, fp2, alpha);
+      // a zero the compiler cannot see through keeps the curvatures inside
+      // this branch (it would otherwise form one per face for reuse by the
+      // next face's branch: two instructions on every face)
+      T zero = T(0);
+      asm volatile("" : "+v"(zero));
+      const T c = mp_clamp(phi, fm1 - fm2, dl + zero, dr + zero, fp2 - fp1, f0, fp1, alpha);
       phib = accept ? phi : c;
     }
     if constexpr (LIM == SLMPP_LIM_MPP) {
@@ -211,7 +222,7 @@ __device__ __forceinline__ void advance(const T* __restrict__ col, int stride, i
 #pragma unroll
   for (int k = 0; k < ORDER; ++k) w[k] = e.w[k];
   const T z = e.z;
-  const T tz = z + z;
+  const T tz = e.tz;
   const int dir = e.dir;
   int r = e.base + dir * (m0 - 1 - H);  // physical cell of r_{m0-1-H}
   const T* ptr = col + r * stride;      // READ_DIRECT walks a pointer
@@ -275,19 +286,20 @@ __device__ __forceinline__ void advance_ct(const T* __restrict__ col, const Penc
 #pragma unroll
   for (int k = 0; k < ORDER; ++k) w[k] = e.w[k];
   const T z = e.z;
-  const T tz = z + z;
+  const T tz = e.tz;
   const T* ptr = col + (e.base + DIR * (m0 - 1 - H)) * STRIDE;
-  T q[WIN];
+  // the whole window of the segment is read before any flux is formed, so
+  // that the LDS reads are in flight together (the branches of the MP and
+  // PP steps would otherwise keep each read next to its first use)
+  constexpr int NQ = RC + WIN;
+  T q[NQ];
 #pragma unroll
-  for (int k = 0; k < WIN; ++k) q[k] = ptr[k * ST];
+  for (int k = 0; k < NQ; ++k) q[k] = ptr[k * ST];
   T f_left = face_flux<T, ORDER, SLMPP_LIM_MPP>(q, w, tz, alpha);
 #pragma unroll
   for (int k = 0; k < RC; ++k) {
-#pragma unroll
-    for (int j = 0; j < WIN - 1; ++j) q[j] = q[j + 1];
-    q[WIN - 1] = ptr[(WIN + k) * ST];
-    const T f_right = face_flux<T, ORDER, SLMPP_LIM_MPP>(q, w, tz, alpha);
-    out[k] = vfma(-z, f_right - f_left, q[H]);
+    const T f_right = face_flux<T, ORDER, SLMPP_LIM_MPP>(q + k + 1, w, tz, alpha);
+    out[k] = vfma(-z, f_right - f_left, q[k + 1 + H]);
     f_left = f_right;
   }
 }
@@ -449,6 +461,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
       need_safe |= src->absN > a.nfast;
     } else {
       ent[jj].z = T(0);
+      ent[jj].tz = T(0);
       ent[jj].base = 0;
       ent[jj].dir = 1;
       ent[jj].absN = 0;
@@ -824,6 +837,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
         need_safe = src->absN > a.nfast;
       } else {
         ent[tid].z = T(0);
+        ent[tid].tz = T(0);
         ent[tid].base = 0;
         ent[tid].dir = 1;
         ent[tid].absN = 0;
@@ -940,50 +954,82 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
 // back into the plane, advances the v_D pencils of the updated plane and
 // streams the planes out: the two sweeps one after the other, cell for
 // cell, for one read and one write of f.  Persistent over tiles of PB
-// consecutive planes; the next tile's data and pencil entries are loaded
-// into registers before the current tile is computed (as in
-// sweep_fast_kernel).  One thread per segment of R cells of every pencil
-// of the tile: PB * N * (N / R) threads, PB planes of 4-16 KB (measured:
-// two 48^2 FP32 planes per workgroup of 384 threads took 1.5x as long as
-// one per workgroup of 192).
+// consecutive planes; the next tile's data are loaded into registers
+// before the current tile is computed (as in sweep_fast_kernel).
+//
+// Threads are segment-major: thread t advances cells s R .. s R + R - 1 of
+// pencil u = t mod (PB N) (plane u / N, pencil u mod N) with s = t / (PB N),
+// so that where PB N is 64 (32^2 planes in pairs, 64^2 planes) every
+// wavefront holds one segment and the wave-uniform skip of the MP bounds
+// (App. A steps 4-7) is lost only in the wavefronts whose segment contains
+// a rejecting face.  With UNI the PB planes of a tile belong to one spatial
+// cell (vouter a multiple of PB): the two pencil entries are uniform over
+// the workgroup and live in scalar registers.  (Four 48^2 planes per
+// workgroup with one segment per wavefront were measured slower than one
+// plane per workgroup: 33-38 ms against 25 ms per pass at 48^3 x 48^3, for
+// want of wavefronts per CU.)
 constexpr int kPlaneFast = 4;  // integer shifts read directly in the plane kernel
 
-template <typename T, int N>
+template <typename T, int ORDER, int N>
 struct PlaneShape {
   static constexpr int R = N == 64 ? 16 : (N == 48 ? 12 : 8);  // cells per thread
   static constexpr int S = N / R;                               // segments per pencil
   static constexpr int PB = sizeof(T) == 4 ? (N == 24 ? 3 : N == 32 ? 2 : 1) : (N == 24 ? 2 : 1);
   static constexpr int threads = PB * N * S;
+  // ring width (shifts up to kPlaneFast cells read the ring directly)
+  static constexpr int G = (ORDER == 7 ? 4 : 3) + kPlaneFast;
+  // odd row pitch: the rows of one plane start on distinct banks
+  static constexpr int P = (N + 2 * G) | 1;
+  // plane stride: the plane's rows padded to N (mod 64) elements, so that
+  // with PB N = 64 the two planes of a wavefront fall on disjoint banks
+  static constexpr int rows = (N + 2 * G) * P;
+  static constexpr int PS = PB == 1 ? rows : rows + (((N - rows) % 64) + 64) % 64;
 };
 
-template <typename T, int ORDER, int N>
-__global__ void __launch_bounds__((PlaneShape<T, N>::threads))
+// A pencil entry read through the constant address space: the tables are
+// not written while a sweep runs, so where the address is uniform over the
+// wavefront the compiler loads the entry with scalar loads and keeps it in
+// scalar registers (its weights then enter the FMAs as scalar operands).
+template <typename T>
+__device__ __forceinline__ PencilEntry<T> load_entry_uniform(const PencilEntry<T>* p) {
+  constexpr int NW = sizeof(PencilEntry<T>) / 4;
+  using CW = const __attribute__((address_space(4))) uint32_t*;
+  const CW q = (CW)(p);
+  uint32_t w[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) w[i] = q[i];
+  PencilEntry<T> e;
+  __builtin_memcpy(&e, w, sizeof(e));
+  return e;
+}
+template <typename P>
+__device__ __forceinline__ P load_ptr_uniform(const P* p) {
+  using CU = const __attribute__((address_space(4))) uint64_t*;
+  return reinterpret_cast<P>(static_cast<uintptr_t>(*(CU)(p)));
+}
+
+template <typename T, int ORDER, int N, bool UNI>
+__global__ void __launch_bounds__((PlaneShape<T, ORDER, N>::threads))
     kick_plane_kernel(SweepArgs a, PlanePlan pl, const PencilEntry<T>* __restrict__ tabA,
                       const PencilEntry<T>* __restrict__ tabB) {
   extern __shared__ __align__(16) unsigned char smem[];
   using V = typename Vec<T>::type;
-  using Sh = PlaneShape<T, N>;
+  using Sh = PlaneShape<T, ORDER, N>;
   constexpr int VN = Vec<T>::N;
   constexpr int R = Sh::R, S = Sh::S, PB = Sh::PB, NT = Sh::threads;
+  constexpr int G = Sh::G, P = Sh::P, PS = Sh::PS;
   constexpr int NN = N * N;
+  constexpr int PN = PB * N;                // pencils of one segment row of the tile
   constexpr int NVEC = PB * NN / VN;       // 16-byte vectors per tile
   constexpr int NV = (NVEC + NT - 1) / NT;  // per thread
   static_assert(N % VN == 0 && N % R == 0 && PB >= 1 && NT <= 1024, "plane shape");
   const int tid = threadIdx.x;
-  // ring width and row pitch are fixed by ORDER and N (shifts up to
-  // kPlaneFast cells read the ring directly); the host plan agrees
-  constexpr int G = (ORDER == 7 ? 4 : 3) + kPlaneFast;
-  constexpr int P = (N + 2 * G) | 1;
-  constexpr int PL = (N + 2 * G) * P;
-  constexpr int SP = P;
   T* lds = reinterpret_cast<T*>(smem);
-  const size_t data_bytes = ((size_t)PB * PL * sizeof(T) + 15) & ~(size_t)15;
-  PencilEntry<T>* ent = reinterpret_cast<PencilEntry<T>*>(smem + data_bytes);
   T* f = reinterpret_cast<T*>(a.f);
   const T alpha = (T)a.alpha;
   // zero the planes with their rings once (interior writes never touch the
   // rings); the barrier orders these stores before the first tile's data
-  for (int e = tid; e < PB * PL; e += NT) lds[e] = T(0);
+  for (int e = tid; e < PB * PS; e += NT) lds[e] = T(0);
   __syncthreads();
   // data movement map: vector k of this thread is tile vector tid + NT k,
   // in plane vq[k] (PB: none) at LDS offset loff[k]
@@ -995,27 +1041,23 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
       const int e = v * VN;
       const int q = e / NN, rem = e - q * NN;
       const int ia = rem / N, ib = rem - ia * N;
-      loff[k] = q * PL + (ia + G) * P + G + ib;
+      loff[k] = q * PS + (ia + G) * P + G + ib;
       vq[k] = q;
     } else {
       loff[k] = 0;
       vq[k] = PB;
     }
   }
-  // compute map: plane cq, pencil cj, cells m0 .. m0 + R - 1
-  const int cq = tid / (N * S);
-  const int cr = tid - cq * (N * S);
-  const int cj = cr % N;
-  const int m0 = (cr / N) * R;
-  const T* colA = lds + cq * PL + G * P + G + cj;    // along v_{D-1}: stride P
-  const T* colB = lds + cq * PL + (G + cj) * P + G;  // along v_D: stride 1
+  // compute map (segment-major): plane cq, pencil cj, cells m0 .. m0 + R - 1
+  const int s = tid / PN;
+  const int u = tid - s * PN;
+  const int cq = u / N;
+  const int cj = u - cq * N;
+  const int m0 = s * R;
+  const T* colA = lds + cq * PS + G * P + G + cj;    // along v_{D-1}: stride P
+  const T* colB = lds + cq * PS + (G + cj) * P + G;  // along v_D: stride 1
 
   V pf[NV];
-  // threads < 2 PB: pencil entry of (plane tid / 2, axis tid % 2), as
-  // 16-byte words
-  constexpr int EW = sizeof(PencilEntry<T>) / 16;
-  static_assert(sizeof(PencilEntry<T>) % 16 == 0, "entry size");
-  V en[EW];
   // several runs of one geometry (batched ensembles): tile tt belongs to
   // run tt / tpr with f fmulti[r] and tables tmulti[r] (v_{D-1}) and
   // tmulti[nrun + r] (v_D); pl.planes counts the planes of one run
@@ -1023,16 +1065,18 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
   int np_next = 0;
   int64_t p0_next = 0;
   T* f_next = f;
+  const PencilEntry<T>* ta_next = tabA;
+  const PencilEntry<T>* tb_next = tabB;
   auto issue = [&](int64_t tt) __attribute__((always_inline)) {
     int64_t lt = tt;
-    const PencilEntry<T>* ta = tabA;
-    const PencilEntry<T>* tb = tabB;
+    ta_next = tabA;
+    tb_next = tabB;
     if (a.fmulti) {
       const int64_t r = tt / a.tpr;
       lt = tt - r * a.tpr;
-      f_next = reinterpret_cast<T*>(a.fmulti[r]);
-      ta = reinterpret_cast<const PencilEntry<T>*>(a.tmulti[r]);
-      tb = reinterpret_cast<const PencilEntry<T>*>(a.tmulti[nrun + r]);
+      f_next = reinterpret_cast<T*>(load_ptr_uniform(a.fmulti + r));
+      ta_next = reinterpret_cast<const PencilEntry<T>*>(load_ptr_uniform(a.tmulti + r));
+      tb_next = reinterpret_cast<const PencilEntry<T>*>(load_ptr_uniform(a.tmulti + nrun + r));
     }
     p0_next = lt * PB;
     np_next = (int)min<int64_t>(PB, pl.planes - p0_next);
@@ -1040,12 +1084,6 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (vq[k] < np_next) pf[k] = __builtin_nontemporal_load(src + tid + NT * k);
-    if (tid < 2 * PB && (tid >> 1) < np_next) {
-      const int64_t ix = udiv(p0_next + (tid >> 1), pl.vouter);
-      const V* src = reinterpret_cast<const V*>((tid & 1) ? tb + ix : ta + ix);
-#pragma unroll
-      for (int w = 0; w < EW; ++w) en[w] = src[w];
-    }
   };
   int64_t t = blockIdx.x;
   if (t < pl.tiles) issue(t);
@@ -1053,55 +1091,58 @@ __global__ void __launch_bounds__((PlaneShape<T, N>::threads))
     const int np = np_next;
     const int64_t p0 = p0_next;
     T* const fc = f_next;
-    if (tid < 2 * PB) {
-      V* dst = reinterpret_cast<V*>(ent + tid);
-#pragma unroll
-      for (int w = 0; w < EW; ++w) dst[w] = en[w];
+    const bool act = cq < np;
+    // the two pencil entries of this thread's plane (with UNI: of every
+    // plane of the tile, read with scalar loads), requested before the
+    // tile's data go to LDS
+    PencilEntry<T> eA{}, eB{};
+    if (UNI || act) {
+      const int64_t pp = UNI ? p0 : p0 + cq;
+      const int64_t ix = pl.vdiv.m ? (int64_t)pl.vdiv.div((uint32_t)pp) : udiv(pp, pl.vouter);
+      eA = load_entry_uniform(ta_next + ix);
+      eB = load_entry_uniform(tb_next + ix);
     }
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (vq[k] < np) put(lds + loff[k], pf[k]);
     __syncthreads();
     if (t + gridDim.x < pl.tiles) issue(t + gridDim.x);
-    const bool act = cq < np;
     T out[R];
     // v_{D-1}
     if (act) {
-      const PencilEntry<T> e = ent[2 * cq];
-      if (e.absN <= kPlaneFast) {
-        if (e.dir > 0)
-          advance_ct<T, ORDER, R, SP, 1>(colA, e, m0, alpha, out);
+      if (eA.absN <= kPlaneFast) {
+        if (eA.dir > 0)
+          advance_ct<T, ORDER, R, P, 1>(colA, eA, m0, alpha, out);
         else
-          advance_ct<T, ORDER, R, SP, -1>(colA, e, m0, alpha, out);
+          advance_ct<T, ORDER, R, P, -1>(colA, eA, m0, alpha, out);
       } else {
-        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colA, SP, N, G, 0, e, m0, R, alpha, out,
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colA, P, N, G, 0, eA, m0, R, alpha, out,
                                                         nullptr);
       }
     }
     __syncthreads();
     if (act) {
-      if (ent[2 * cq].dir > 0)
-        store_ct<T, R, SP, 1>(const_cast<T*>(colA), N, m0, out);
+      if (eA.dir > 0)
+        store_ct<T, R, P, 1>(const_cast<T*>(colA), N, m0, out);
       else
-        store_ct<T, R, SP, -1>(const_cast<T*>(colA), N, m0, out);
+        store_ct<T, R, P, -1>(const_cast<T*>(colA), N, m0, out);
     }
     __syncthreads();
     // v_D on the updated plane
     if (act) {
-      const PencilEntry<T> e = ent[2 * cq + 1];
-      if (e.absN <= kPlaneFast) {
-        if (e.dir > 0)
-          advance_ct<T, ORDER, R, 1, 1>(colB, e, m0, alpha, out);
+      if (eB.absN <= kPlaneFast) {
+        if (eB.dir > 0)
+          advance_ct<T, ORDER, R, 1, 1>(colB, eB, m0, alpha, out);
         else
-          advance_ct<T, ORDER, R, 1, -1>(colB, e, m0, alpha, out);
+          advance_ct<T, ORDER, R, 1, -1>(colB, eB, m0, alpha, out);
       } else {
-        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colB, 1, N, G, 0, e, m0, R, alpha, out,
+        advance<T, ORDER, SLMPP_LIM_MPP, READ_SAFE, R>(colB, 1, N, G, 0, eB, m0, R, alpha, out,
                                                         nullptr);
       }
     }
     __syncthreads();
     if (act) {
-      if (ent[2 * cq + 1].dir > 0)
+      if (eB.dir > 0)
         store_ct<T, R, 1, 1>(const_cast<T*>(colB), N, m0, out);
       else
         store_ct<T, R, 1, -1>(const_cast<T*>(colB), N, m0, out);
@@ -1154,8 +1195,9 @@ __device__ __forceinline__ PencilEntry<T> pencil_entry(const SweepArgs& a, int i
   PencilEntry<T> e{};
   e.dir = mirror ? -1 : 1;
   e.base = (int32_t)((mirror ? (int64_t)(n - 1) : 0) - N);
-  e.absN = (int32_t)(N < 0 ? -N : N);
+  e.absN = (int16_t)(N < 0 ? -N : N);
   e.z = (T)az;
+  e.tz = (T)(az + az);
   // an RK stage takes the interface interpolation itself: the flux
   // polynomial at zero Courant number
   const double zw = a.rk ? 0.0 : az;
@@ -1543,17 +1585,17 @@ hipError_t launch_sweep(int dtype, int order, int limiter, const SweepArgs& a, c
 }
 
 namespace {
-template <typename T, int ORDER, int N>
-hipError_t launch_plane_t(const SweepArgs& a, const PlanePlan& p, const void* tabA,
+template <typename T, int ORDER, int N, bool UNI>
+hipError_t launch_plane_u(const SweepArgs& a, const PlanePlan& p, const void* tabA,
                           const void* tabB, hipStream_t s) {
-  auto kern = kick_plane_kernel<T, ORDER, N>;
+  auto kern = kick_plane_kernel<T, ORDER, N, UNI>;
   if (p.lds_bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)p.lds_bytes);
     if (e != hipSuccess) return e;
   }
-  constexpr int NT = PlaneShape<T, N>::threads;
+  constexpr int NT = PlaneShape<T, ORDER, N>::threads;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, reinterpret_cast<const void*>(kern), NT, p.lds_bytes);
@@ -1572,6 +1614,13 @@ hipError_t launch_plane_t(const SweepArgs& a, const PlanePlan& p, const void* ta
   return hipGetLastError();
 }
 
+template <typename T, int ORDER, int N>
+hipError_t launch_plane_t(const SweepArgs& a, const PlanePlan& p, const void* tabA,
+                          const void* tabB, hipStream_t s) {
+  return p.uni ? launch_plane_u<T, ORDER, N, true>(a, p, tabA, tabB, s)
+               : launch_plane_u<T, ORDER, N, false>(a, p, tabA, tabB, s);
+}
+
 template <typename T, int ORDER>
 hipError_t launch_plane_o(const SweepArgs& a, const PlanePlan& p, const void* tabA,
                           const void* tabB, hipStream_t s) {
@@ -1583,6 +1632,27 @@ hipError_t launch_plane_o(const SweepArgs& a, const PlanePlan& p, const void* ta
     default: return hipErrorInvalidValue;
   }
 }
+
+// the host's copy of PlaneShape
+template <typename T, int ORDER, int N>
+void plane_shape(PlanePlan& p) {
+  using Sh = PlaneShape<T, ORDER, N>;
+  p.N = N;
+  p.PB = Sh::PB;
+  p.G = Sh::G;
+  p.pitch = Sh::P;
+  p.plane_lds = Sh::PS;
+}
+template <typename T, int ORDER>
+bool plane_shape_n(int N, PlanePlan& p) {
+  switch (N) {
+    case 24: plane_shape<T, ORDER, 24>(p); return true;
+    case 32: plane_shape<T, ORDER, 32>(p); return true;
+    case 48: plane_shape<T, ORDER, 48>(p); return true;
+    case 64: plane_shape<T, ORDER, 64>(p); return true;
+    default: return false;
+  }
+}
 }  // namespace
 
 PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t planes,
@@ -1590,21 +1660,18 @@ PlanePlan plan_kick_plane(int dtype, int order, int32_t na, int32_t nb, int64_t 
   PlanePlan p{};
   if (na != nb || !(na == 24 || na == 32 || na == 48 || na == 64) || planes < 1 || vouter < 1)
     return p;
-  const int N = na;
-  p.N = N;
-  if (dtype == SLMPP_F64)
-    p.PB = N == 24 ? 2 : 1;
-  else
-    p.PB = N == 24 ? 3 : (N == 32 ? 2 : 1);  // as PlaneShape
-  p.G = (order == 7 ? 4 : 3) + kPlaneFast;  // as in kick_plane_kernel
-  p.pitch = (N + 2 * p.G) | 1;  // odd: lanes walking rows hit distinct banks
-  p.plane_lds = (N + 2 * p.G) * p.pitch;
+  const bool ok = dtype == SLMPP_F64
+                      ? (order == 7 ? plane_shape_n<double, 7>(na, p) : plane_shape_n<double, 5>(na, p))
+                      : (order == 7 ? plane_shape_n<float, 7>(na, p) : plane_shape_n<float, 5>(na, p));
+  if (!ok) return PlanePlan{};
   p.planes = planes;
   p.vouter = vouter;
   p.tiles = (planes + p.PB - 1) / p.PB;
+  // every tile's planes belong to one spatial cell: one pair of entries
+  p.uni = vouter % p.PB == 0 ? 1 : 0;
+  if (planes < ((int64_t)1 << 32) && vouter < ((int64_t)1 << 31)) p.vdiv = FastDiv32::of((uint32_t)vouter);
   const size_t es = dtype == SLMPP_F64 ? 8 : 4;
-  const size_t data = ((size_t)p.PB * p.plane_lds * es + 15) & ~(size_t)15;
-  const size_t lds = data + 2 * (size_t)p.PB * entry_bytes(dtype);
+  const size_t lds = ((size_t)p.PB * p.plane_lds * es + 15) & ~(size_t)15;  // entries: registers
   p.lds_bytes = lds <= 80 * 1024 ? lds : 0;
   return p;
 }

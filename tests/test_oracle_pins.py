@@ -148,6 +148,23 @@ def test_pp_theta_closed_form(oracle):
     assert got == pytest.approx(th * -5.0 + (1 - th) * 1.0, rel=1e-15)
 
 
+def test_pp_is_continuous_below_half_courant_and_jumps_above(oracle):
+    """With nu <= 1/2 the limited flux is continuous in Phibar: where U+
+    changes sign theta = U^UP / (U^UP - U+) -> 1 (U^UP = (1 - 2 nu) f_i
+    >= 0).  Above 1/2 U^UP < 0, theta drops from 1 to 0 at the sign change
+    and the flux jumps from f_i / (2 nu) to f_i (the PP property itself
+    needs nu < 1/2, Sec. 2.1.1)."""
+    eps = 1e-9
+    for nu in (0.2, 0.4, 0.5):
+        t = 1.0 / (2 * nu)  # U+ = 0 at Phibar = f_i / (2 nu), f_i = 1
+        below, above = oracle.pp(t - eps, 1.0, 1.0, nu), oracle.pp(t + eps, 1.0, 1.0, nu)
+        assert abs(above - below) <= 1e-8, nu
+    nu = 0.9
+    t = 1.0 / (2 * nu)
+    assert oracle.pp(t - eps, 1.0, 1.0, nu) == pytest.approx(t, abs=1e-8)
+    assert oracle.pp(t + eps, 1.0, 1.0, nu) == 1.0
+
+
 def test_pp_keeps_random_pencils_non_negative(oracle):
     """Positivity (Sec. 2.1.1): f >= 0 and |zeta| <= 1/2 give f^{n+1} >= 0,
     for any integer shift, on data with zeros and large spikes.  In floating
