@@ -203,6 +203,22 @@ slmpp_status slmpp_advect_x(slmpp_ctx* ctx, int32_t dim, double dt);
  * the device), Eq. (adv_vel).  In place. */
 slmpp_status slmpp_advect_v(slmpp_ctx* ctx, int32_t dim, double dt, const double* accel_dev);
 
+/* slmpp_advect_v without a context and without any workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  desc describes the grid
+ * of f_dev (caller-owned, 16-byte aligned, the grid's cells in its storage
+ * type); accel_dev (prod(nx) doubles) and dt as for slmpp_advect_v; the
+ * work is enqueued on hip_stream (NULL = the null stream) and the result
+ * equals slmpp_advect_v's bit for bit.  The pencil table lives in a 16 MiB
+ * device array of the library that each GPU holds from its first call
+ * until the process ends: grids whose table (one 48-byte FP32 or 80-byte
+ * FP64 entry per spatial cell) exceeds it return SLMPP_ERR_SHAPE.  All
+ * calls on one GPU share that array, so calls that overlap on one GPU (on
+ * different streams, or from several host threads) race.  Not with
+ * SLMPP_FLAG_RK3 (SLMPP_ERR_INVALID).  Errors: slmpp_last_error(NULL). */
+slmpp_status slmpp_advect_v_noalloc(const slmpp_grid_desc* desc, void* f_dev, int32_t dim,
+                                    double dt, const double* accel_dev, void* hip_stream);
+
 /* One velocity kick: SL steps along v_1, .., v_D in that order, each by dt
  * with the context's acceleration (computed from f first when f changed
  * since the last field solve), as in the half-kicks of slmpp_step: the last

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -168,6 +169,36 @@ namespace {
 slmpp_status check_desc(const slmpp_grid_desc* d, std::string& msg) { return check_grid_desc(d, msg); }
 }  // namespace
 
+namespace {
+// The arguments of the sweep along v_l (array axis D + l) of a grid with
+// axis sizes dims[0..2D), speed accel[ix] (Eq. (adv_vel)).
+SweepArgs v_sweep_args(const slmpp_grid_desc& d, const int64_t* dims, int l, double dt,
+                       const double* accel, void* f, int64_t& inner) {
+  const int D = d.D, nd = 2 * D, a = D + l;
+  inner = 1;
+  for (int k = a + 1; k < nd; ++k) inner *= dims[k];
+  int64_t outer = 1, xdiv = 1;
+  for (int k = 0; k < a; ++k) outer *= dims[k];
+  for (int k = D; k < a; ++k) xdiv *= dims[k];
+  SweepArgs s{};
+  s.f = f;
+  s.npen = outer * inner;
+  s.inner = inner;
+  s.n = (int32_t)dims[a];
+  s.dt = dt;
+  s.alpha = d.alpha;
+  s.cmode = SPEED_FROM_ACCEL;
+  s.accel = accel;
+  s.xdiv = xdiv;
+  s.vdiv = 1;
+  s.nvl = 1;
+  s.h = (d.v_hi[l] - d.v_lo[l]) / (double)d.nv[l];
+  s.bc = d.v_bc;
+  s.nfast = 4;
+  return s;
+}
+}  // namespace
+
 struct slmpp_ctx {
   slmpp_grid_desc d{};
   void* f = nullptr;
@@ -298,7 +329,9 @@ struct slmpp_ctx {
     s.n = (int32_t)dims[a];
     s.dt = dt;
     s.alpha = d.alpha;
-    if (a < D) {  // x_l sweep, speed v_l
+    if (a >= D) {  // v_l sweep, speed a_l(x)
+      s = v_sweep_args(d, dims, a - D, dt, accel_dev, f, inner);
+    } else {  // x_l sweep, speed v_l
       const int l = a;
       int64_t vdiv = 1;
       for (int k = D + l + 1; k < nd; ++k) vdiv *= dims[k];
@@ -315,18 +348,6 @@ struct slmpp_ctx {
         slmpp_status st = check_rk_x(l, dt);
         if (st != SLMPP_OK) return st;
       }
-    } else {  // v_l sweep, speed a_l(x)
-      const int l = a - D;
-      int64_t xdiv = 1;
-      for (int k = D; k < a; ++k) xdiv *= dims[k];
-      s.cmode = SPEED_FROM_ACCEL;
-      s.accel = accel_dev;
-      s.xdiv = xdiv;
-      s.vdiv = 1;
-      s.nvl = 1;
-      s.h = hv[l];
-      s.bc = d.v_bc;
-      s.nfast = 4;
     }
     if (rk) {
       s.rk = 1;
@@ -504,6 +525,36 @@ slmpp_status sync_status(slmpp_ctx* c) {
   return SLMPP_OK;
 }
 
+}  // namespace
+
+namespace {
+// Device memory of slmpp_advect_v_noalloc: one pencil table, in a
+// file-scope array that every GPU the library runs on holds until the
+// process ends (no allocation call).  Host code never uses the array's
+// name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress and kept per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
 }  // namespace
 
 extern "C" {
@@ -768,6 +819,69 @@ slmpp_status slmpp_advect_v(slmpp_ctx* c, int32_t dim, double dt, const double* 
   c->field_valid = false;
   if (dt == 0.0) return SLMPP_OK;
   return c->sweep(c->D + dim, dt, accel_dev);
+}
+
+slmpp_status slmpp_advect_v_noalloc(const slmpp_grid_desc* desc, void* f_dev, int32_t dim,
+                                    double dt, const double* accel_dev, void* hip_stream) {
+  std::string msg;
+  slmpp_status st = check_desc(desc, msg);
+  if (st != SLMPP_OK) {
+    g_error = msg;
+    return st;
+  }
+  if (!f_dev || !accel_dev) {
+    g_error = "f_dev and accel_dev must be non-NULL";
+    return SLMPP_ERR_INVALID;
+  }
+  if (reinterpret_cast<uintptr_t>(f_dev) % 16 != 0) {
+    g_error = "f_dev must be 16-byte aligned";
+    return SLMPP_ERR_INVALID;
+  }
+  if (dim < 0 || dim >= desc->D) {
+    g_error = "dim " + std::to_string(dim) + " outside 0.." + std::to_string(desc->D - 1);
+    return SLMPP_ERR_INVALID;
+  }
+  if (!std::isfinite(dt)) {
+    g_error = "dt is not finite";
+    return SLMPP_ERR_NONFINITE;
+  }
+  if (desc->flags & SLMPP_FLAG_RK3) {
+    g_error = "RK3 time integration needs a workspace copy of f: use slmpp_advect_v";
+    return SLMPP_ERR_INVALID;
+  }
+  const int D = desc->D;
+  int64_t dims[6];
+  for (int l = 0; l < D; ++l) {
+    dims[l] = desc->nx[l];
+    dims[D + l] = desc->nv[l];
+  }
+  const int64_t nxs = n_space(*desc);
+  const size_t need = pencil_table_bytes(desc->storage, nxs);
+  if (need > kNoAllocScratchBytes) {
+    g_error = "velocity sweep of " + std::to_string(nxs) + " spatial cells needs " +
+              std::to_string(need) + " bytes of scratch; the limit is " +
+              std::to_string(kNoAllocScratchBytes) + " (use slmpp_advect_v)";
+    return SLMPP_ERR_SHAPE;
+  }
+  if (dt == 0.0) return SLMPP_OK;
+  int64_t inner = 1;
+  const SweepArgs s = v_sweep_args(*desc, dims, dim, dt, accel_dev, f_dev, inner);
+  const SweepPlan p = plan_sweep(desc->storage, desc->order, desc->limiter, s.n, s.npen, inner,
+                                 s.nfast);
+  if (p.lds_bytes > 160 * 1024) {
+    g_error = "pencil of " + std::to_string(s.n) + " cells does not fit the LDS tile";
+    return SLMPP_ERR_SHAPE;
+  }
+  void* table = nullptr;
+  hipError_t e = scratch_for_current_device(&table);
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  if (e == hipSuccess) e = launch_pencil_table(desc->storage, desc->order, s, table, nxs, stream);
+  if (e == hipSuccess) e = launch_sweep(desc->storage, desc->order, desc->limiter, s, p, table, stream);
+  if (e != hipSuccess) {
+    g_error = std::string("advect_v_noalloc: ") + hipGetErrorString(e);
+    return SLMPP_ERR_DEVICE;
+  }
+  return SLMPP_OK;
 }
 
 slmpp_status slmpp_kick(slmpp_ctx* c, double dt) {

@@ -95,6 +95,7 @@ SIGNATURES = {
     "slmpp_init_f_separable": (_S, [_VP, _VP, _VP, _VP, _VP]),
     "slmpp_advect_x": (_S, [_VP, _I32, _D]),
     "slmpp_advect_v": (_S, [_VP, _I32, _D, _VP]),
+    "slmpp_advect_v_noalloc": (_S, [_VP, _VP, _I32, _D, _VP, _VP]),
     "slmpp_kick": (_S, [_VP, ctypes.c_double]),
     "slmpp_density_moment": (_S, [_VP, _VP]),
     "slmpp_poisson_solve": (_S, [_VP, _VP, _VP, _VP]),
@@ -338,6 +339,18 @@ class Context:
         acc = np.empty(self.desc.D * self.nxs, dtype=np.float64)
         self._c(lib().slmpp_get_field(self.h, rho.ctypes.data_as(_VP), acc.ctypes.data_as(_VP)))
         return rho, acc
+
+
+def advect_v_noalloc(desc: GridDesc, f, dim, dt, accel, stream=None):
+    """slmpp_advect_v_noalloc: one velocity sweep of the grid `desc` held in
+    the CUDA tensor f (no context, no workspace); accel: CUDA float64 tensor
+    of prod(nx) values.  Enqueued on `stream` (a torch.cuda.Stream; the
+    current stream if None)."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(f.device)
+    _check(lib().slmpp_advect_v_noalloc(ctypes.byref(desc), _VP(f.data_ptr()), int(dim), float(dt),
+                                        _VP(accel.data_ptr()), _VP(s.cuda_stream)))
 
 
 def copy_device(dst_ptr, src_ptr, nbytes, stream=None):

@@ -207,3 +207,22 @@ def test_isolated_flag_needs_three_dimensions():
     assert slmpp.validate(d3)[0] == slmpp.OK
     plain = slmpp.make_desc(dict(workloads.collapse_3d3v(nx=8, nv=4), field_bc="periodic"))
     assert slmpp.workspace_bytes(d3) >= slmpp.workspace_bytes(plain) + 40 * 8 * 512
+
+
+def test_advect_v_noalloc_rejects_before_touching_the_device():
+    """Argument errors of the allocation-free velocity sweep come back before
+    any device call (fake, never dereferenced device pointers)."""
+    L = slmpp.lib()
+    d = _desc()
+    fake = ctypes.c_void_p(4096)
+    st = L.slmpp_advect_v_noalloc(ctypes.byref(d), fake, 1, 0.1, fake, None)
+    assert st == slmpp.ERR_INVALID  # dim outside 0..D-1
+    st = L.slmpp_advect_v_noalloc(ctypes.byref(d), fake, 0, float("nan"), fake, None)
+    assert st == slmpp.ERR_NONFINITE
+    st = L.slmpp_advect_v_noalloc(ctypes.byref(d), None, 0, 0.1, fake, None)
+    assert st == slmpp.ERR_INVALID
+    # a table beyond the 16 MiB scratch: 64^3 spatial cells in FP64 (80 B each)
+    big = slmpp.make_desc(workloads.landau_3d3v(n=64, nv=4), slmpp.F64)
+    st = L.slmpp_advect_v_noalloc(ctypes.byref(big), fake, 0, 0.1, fake, None)
+    assert st == slmpp.ERR_SHAPE
+    assert b"scratch" in L.slmpp_last_error(None)
