@@ -71,27 +71,80 @@ def read_traffic(kernel_key):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(spec_fn, n_sample):
-    """FP64 oracle: one Strang step of the same workload at n_sample^6."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spec_fn, n_nproc, n_one, repeats=5):
+    """The FP64 oracle built -O3 -march=native, timed per sweep on this
+    host: every axis of the workload at n_nproc^D x n_nproc^D with the
+    host's thread share, and at n_one^D x n_one^D with one thread; one
+    warm-up and `repeats` timed sweeps per axis, the median kept.  The cost
+    per cell is flat in the grid size (pencil by pencil), so the rates stand
+    for the full-size workload."""
+    import statistics
+
     import oracle as O
 
-    s = spec_fn(n_sample)
-    run = O.Run(s)
-    t0 = time.perf_counter()
-    run.step(s["dt"], 1)
-    dt = time.perf_counter() - t0
-    cells = 1
-    for l in range(s["D"]):
-        cells *= s["nx"][l] * s["nv"][l]
-    sweeps = 3 * s["D"]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.use_native()
+    nproc = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    legs = {}
+    t_all = time.perf_counter()
+    for threads, n in ((nproc, n_nproc), (1, n_one)):
+        O.set_threads(threads)
+        s = spec_fn(n)
+        grid = O.make_grid(s)
+        f = O.init_separable(grid, *__import__("paper_1702_08521_amd.workloads",
+                                               fromlist=["x"]).separable_factors(s))
+        acc = O.field(grid, f)
+        D = s["D"]
+        cells = 1
+        for l in range(D):
+            cells *= s["nx"][l] * s["nv"][l]
+        nxs = grid.n_space
+        per_axis = {}
+        for axis in range(2 * D):
+            if axis < D:
+                sweep = lambda: O.advect_x(grid, f, axis, s["dt"])  # noqa: E731
+            else:
+                comp = acc[(axis - D) * nxs:(axis - D + 1) * nxs]
+                sweep = lambda: O.advect_v(grid, f, axis - D, 0.5 * s["dt"], comp)  # noqa: E731
+            sweep()
+            ts = []
+            for _ in range(repeats):
+                t0 = time.perf_counter()
+                sweep()
+                ts.append(time.perf_counter() - t0)
+            name = ("x%d" % (axis + 1)) if axis < D else ("v%d" % (axis - D + 1))
+            per_axis[name] = cells / statistics.median(ts)
+        # a Strang step sweeps every x axis once and every v axis twice
+        weights = {k: (1 if k[0] == "x" else 2) for k in per_axis}
+        t_step = sum(w / per_axis[k] for k, w in weights.items())
+        legs[threads] = {"grid": f"{n}^{D} x {n}^{D}", "cells": cells,
+                         "cell_updates_per_s": sum(weights.values()) / t_step,
+                         "per_axis": {k: round(v, 1) for k, v in per_axis.items()}}
+        log(f"[bench] cpu baseline {threads} thread(s) at {n}^{D}x{n}^{D}: "
+            f"{legs[threads]['cell_updates_per_s']:.3e} cell-updates/s per sweep")
+    wall = time.perf_counter() - t_all
     return {
-        "value": sweeps * cells / dt,
+        "value": legs[nproc]["cell_updates_per_s"],
         "unit": "cell-updates/s",
-        "cores": threads,
+        "cores": nproc,
         "kind": "oracle",
-        "sample": f"one Strang step ({sweeps} sweeps + moment + Poisson), FP64, "
-                  f"{s['name']} at {s['nx'][0]}^{s['D']} x {s['nv'][0]}^{s['D']}, {dt:.2f} s",
+        "sample": (f"FP64 oracle, gcc -O3 -march=native -ffp-contract=off, OpenMP over pencils, on "
+                   f"{cpu_model()} ({os.cpu_count()} CPUs, {nproc} threads used); median of "
+                   f"{repeats} timed sweeps after one warm-up, every axis, weighted as in a "
+                   f"Strang step (x once, v twice): {nproc} threads at {n_nproc}^6, 1 thread at "
+                   f"{n_one}^6 (per cell, the cost being linear in cells); {wall:.1f} s"),
+        "single_thread": {"value": legs[1]["cell_updates_per_s"], "cores": 1,
+                          "grid": legs[1]["grid"], "per_axis": legs[1]["per_axis"]},
+        "per_axis": legs[nproc]["per_axis"],
     }
 
 
@@ -226,7 +279,10 @@ def main():
     ap.add_argument("--workload", default="landau_3d3v")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=24,
+                    help="grid side of the oracle's timing with the host's thread share")
+    ap.add_argument("--cpu-sample-1t", type=int, default=16,
+                    help="grid side of the oracle's single-thread timing")
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps of the whole ensemble in its cpu_baseline (--workload ensemble)")
     ap.add_argument("--merge-compare", type=int, default=6,
@@ -495,7 +551,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline at {args.cpu_sample}^{D}")
+        log(f"[bench] cpu baseline at {args.cpu_sample}^{D} and {args.cpu_sample_1t}^{D}")
 
         def spec_fn(n):
             if args.workload == "landau_3d3v":
@@ -506,7 +562,7 @@ def main():
                 return W.collapse_3d3v(nx=n, nv=n // 2, order=5)
             return workload(args.workload, args.dtype)
 
-        out["cpu_baseline"] = cpu_baseline(spec_fn, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(spec_fn, args.cpu_sample, args.cpu_sample_1t)
     print(json.dumps(out), flush=True)
 
 

@@ -30,15 +30,30 @@ TIME_SL = 0
 TIME_RK3 = 1
 
 
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+_use_native = False
+
+
 def build(native: bool = False) -> str:
-    """Compile the oracle with gcc.  ``native`` adds -O3 -march=native (the
-    arithmetic is unchanged: contraction stays off)."""
+    """Compile the oracle with gcc.  ``native``: -O3 -march=native into a
+    library of its own (the arithmetic is unchanged: contraction stays off,
+    no fast-math), used only to time the oracle."""
+    out = _LIB_NATIVE if native else _LIB
     opt = ["-O3", "-march=native"] if native else ["-O2"]
     cmd = ["gcc", *opt, "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-Wall", _SRC, "-o", _LIB + ".tmp", "-lm"]
+           "-shared", "-Wall", _SRC, "-o", out + ".tmp", "-lm"]
     subprocess.check_call(cmd)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def use_native():
+    """Switch this process to the -O3 -march=native build (built on first
+    use).  Call before the first oracle call."""
+    global _use_native, _lib
+    if _lib is not None and not _use_native:
+        raise RuntimeError("the oracle library is already loaded")
+    _use_native = True
 
 
 class Grid(ctypes.Structure):
@@ -109,9 +124,10 @@ _P = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = _LIB_NATIVE if _use_native else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(native=_use_native)
+        L = ctypes.CDLL(path)
         sig = {
             "oracle_minmod2": (_D, [_D, _D]),
             "oracle_minmod4": (_D, [_D, _D, _D, _D]),
@@ -140,6 +156,8 @@ def lib():
             "oracle_init_separable": (None, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P]),
             "oracle_mass": (_D, [ctypes.POINTER(Grid), _P]),
             "oracle_abi_version": (_I, []),
+            "oracle_set_threads": (None, [_I]),
+            "oracle_max_threads": (_I, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -310,6 +328,15 @@ def init_separable(grid, s, gv):
     lib().oracle_init_separable(ctypes.byref(grid), _ptr(f), _ptr(s), _ptr(gs[0]),
                                 _ptr(gs[1]), _ptr(gs[2]))
     return f
+
+
+def set_threads(n):
+    """Threads of the oracle's loops over pencils (timing only)."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().oracle_max_threads())
 
 
 def mass(grid, f):

@@ -56,6 +56,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_BC_PERIODIC 0
 #define ORACLE_BC_OUTFLOW 1
@@ -902,3 +905,21 @@ double oracle_mass(const oracle_grid* g, const double* f) {
 }
 
 int oracle_abi_version(void) { return 1; }
+
+/* Threads of the OpenMP loops over pencils (for timing the oracle; the
+ * pencils are independent, so the results do not depend on it). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
