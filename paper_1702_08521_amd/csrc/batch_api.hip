@@ -73,6 +73,12 @@ constexpr int kMinW = 8;
 
 struct Layout {
   std::vector<size_t> rho, phi, acc, tab, tab2;
+  // the pencil tables of the step, computed outside the sweep phases: per
+  // run and axis l, xt[r * 3 + l] for the x_l sweeps (fixed: dt does not
+  // change) and vt[(r * 3 + l) * 2 + k] for the v_l sweeps with dt / 2
+  // (k = 0) and, with merged kicks, dt (k = 1) (after every field solve)
+  std::vector<size_t> xt, vt;
+  size_t tsweeps;  // BatchSweep lists of those table computations
   size_t runs, sweeps, items, mitems, mitems2, mom, reduce, ptrs, scratch, stage, total;
   int64_t max_sweeps, max_items, nmitems, stage_doubles, mom_doubles;
 };
@@ -107,6 +113,11 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
     L.tab.push_back(take(pencil_table_bytes(SLMPP_F64, std::max(maxnv, g.nxs))));
     // v_{D-1} table of a two-axis kick pass
     L.tab2.push_back(take(g.D >= 2 ? pencil_table_bytes(SLMPP_F64, g.nxs) : 0));
+    for (int l = 0; l < 3; ++l) {
+      L.xt.push_back(l < g.D ? take(pencil_table_bytes(SLMPP_F64, d[r].nv[l])) : 0);
+      for (int k = 0; k < 2; ++k)
+        L.vt.push_back(l < g.D && (k == 0 || merged) ? take(pencil_table_bytes(SLMPP_F64, g.nxs)) : 0);
+    }
     // work items: every sweep of a step at the smallest tile width
     for (int a = 0; a < 2 * g.D; ++a) {
       const int64_t npen = g.ncell / g.dims[a];
@@ -118,6 +129,7 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
     stage = std::max(stage, g.nxs + sumnv);
   }
   L.max_sweeps = (int64_t)n * (1 + kicks) * Dmax + 2 * (int64_t)n;
+  L.tsweeps = take(sizeof(BatchSweep) * 9 * (size_t)n);
   L.runs = take(sizeof(BatchRun) * n);
   L.sweeps = take(sizeof(BatchSweep) * L.max_sweeps);
   L.items = take(sizeof(BatchItem) * std::max<int64_t>(L.max_items, 1));
@@ -255,6 +267,16 @@ struct slmpp_batch {
   T* at(size_t off) {
     return reinterpret_cast<T*>(work + off);
   }
+
+  // The pencil table of run r for a sweep of slot kind sd (see Layout::xt, vt).
+  void* table_of(int r, const SlotDef& sd) {
+    if (!sd.vel) return work + lay.xt[(size_t)r * 3 + sd.l];
+    return work + lay.vt[((size_t)r * 3 + sd.l) * 2 + (sd.frac == 1.0 ? 1 : 0)];
+  }
+  // table computations done outside the phases: the x tables once per
+  // build, the v tables after every field solve (BatchSweep lists at
+  // lay.tsweeps: nxt x entries, then nvt v entries)
+  int nxt = 0, nvt = 0, xt_max = 0, vt_max = 0;
 
   // Sweep arguments of run r for slot s (nullptr-table entries filled in).
   bool sweep_of(int r, const SlotDef& sd, SweepArgs& a, int64_t& count) const {
@@ -398,11 +420,11 @@ struct slmpp_batch {
             BatchSweep ta{}, tb{};
             int64_t ca = 0;
             sweep_of(r, sa, ta.a, ca);
-            ta.table = work + lay.tab2[r];
+            ta.table = table_of(r, sa);
             ta.order = d[r].order;
             ta.count = (int32_t)ca;
             tb.a = args[r];
-            tb.table = work + lay.tab[r];
+            tb.table = table_of(r, slots[si]);
             tb.order = d[r].order;
             tb.count = (int32_t)counts[r];
             sweeps.push_back(ta);
@@ -435,7 +457,7 @@ struct slmpp_batch {
         fg.p.tiles = fplan[r0].tiles * (int64_t)rs.size();
         const size_t off = group_ptrs.size();
         for (int r : rs) group_ptrs.push_back(f[r]);
-        for (int r : rs) group_ptrs.push_back(work + lay.tab[r]);
+        for (int r : rs) group_ptrs.push_back(table_of(r, slots[si]));
         fg.a.fmulti = dptrs + off;
         fg.a.tmulti = const_cast<const void* const*>(dptrs + off + rs.size());
         for (int r : rs) grouped[r] = 1;
@@ -475,7 +497,7 @@ struct slmpp_batch {
           BatchSweep b{};
           b.a = a;
           b.p = fplan[r];
-          b.table = work + lay.tab[r];
+          b.table = table_of(r, slots[si]);
           b.order = d[r].order;
           b.count = (int32_t)count;
           sweeps.push_back(b);
@@ -500,7 +522,7 @@ struct slmpp_batch {
         BatchSweep b{};
         b.a = a;
         b.p = p;
-        b.table = work + lay.tab[r];
+        b.table = table_of(r, slots[si]);
         b.order = d[r].order;
         b.count = (int32_t)count;
         const int sidx = (int)sweeps.size();
@@ -523,8 +545,8 @@ struct slmpp_batch {
         const size_t off = group_ptrs.size();
         for (int r : rs) group_ptrs.push_back(f[r]);
         for (int r : rs) slot_bytes[si] += 2.0 * es * (double)g[r].ncell;
-        for (int r : rs) group_ptrs.push_back(work + lay.tab2[r]);
-        for (int r : rs) group_ptrs.push_back(work + lay.tab[r]);
+        for (int r : rs) group_ptrs.push_back(table_of(r, SlotDef{true, g[r].D - 2, slots[si].frac}));
+        for (int r : rs) group_ptrs.push_back(table_of(r, slots[si]));
         pg.a.fmulti = dptrs + off;
         pg.a.tmulti = const_cast<const void* const*>(dptrs + off + rs.size());
         pgroups.push_back(pg);
@@ -576,6 +598,31 @@ struct slmpp_batch {
     if (e == hipSuccess && !mitems2.empty())
       e = hipMemcpyAsync(at<int2>(lay.mitems2), mitems2.data(), sizeof(int2) * mitems2.size(),
                          hipMemcpyHostToDevice, stream);
+    // the tables of the step's sweeps: x axes (fixed, computed now), v axes
+    // (recomputed with the field)
+    std::vector<BatchSweep> tl;
+    xt_max = vt_max = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int r = 0; r < nruns; ++r)
+        for (int l = 0; l < g[r].D; ++l)
+          for (int k = 0; k < (pass == 0 ? 1 : (merged ? 2 : 1)); ++k) {
+            const SlotDef sd{pass == 1, l, pass == 1 && k == 0 ? 0.5 : 1.0};
+            BatchSweep t{};
+            int64_t count = 0;
+            sweep_of(r, sd, t.a, count);
+            t.table = table_of(r, sd);
+            t.order = d[r].order;
+            t.count = (int32_t)count;
+            tl.push_back(t);
+            int& mx = pass == 0 ? xt_max : vt_max;
+            mx = std::max<int>(mx, (int)count);
+          }
+    nxt = nvt = 0;
+    for (const BatchSweep& t : tl) (t.a.cmode == SPEED_FROM_VELOCITY ? nxt : nvt) += 1;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(at<BatchSweep>(lay.tsweeps), tl.data(), sizeof(BatchSweep) * tl.size(),
+                         hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_batch_tables(dtype, at<BatchSweep>(lay.tsweeps), nxt, xt_max, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "upload of batch work lists");
     drop_graph();
@@ -594,8 +641,7 @@ struct slmpp_batch {
   hipError_t enqueue_slot(int si, hipStream_t s) {
     const SlotLaunch& L = launches[si];
     if (L.nsweeps == 0) return hipSuccess;
-    const BatchSweep* sw = at<BatchSweep>(lay.sweeps) + L.first_sweep;
-    hipError_t e = launch_batch_tables(dtype, sw, L.nsweeps, L.max_count, s);
+    hipError_t e = hipSuccess;  // the tables were computed at build or with the field
     for (int k = 0; k < L.ngroups && e == hipSuccess; ++k) {
       const FastGroup& fg = groups[(size_t)(L.first_group + k)];
       e = launch_sweep(dtype, fg.order, SLMPP_LIM_MPP, fg.a, fg.p, nullptr, s);
@@ -625,6 +671,9 @@ struct slmpp_batch {
       e = launch_batch_moment(dtype, at<BatchRun>(lay.runs), at<int2>(lay.mitems), (int)lay.nmitems, s);
     }
     if (e == hipSuccess) e = launch_batch_poisson(at<BatchRun>(lay.runs), nruns, max_nxs, s);
+    // the velocity sweeps' tables with the new acceleration
+    if (e == hipSuccess)
+      e = launch_batch_tables(dtype, at<BatchSweep>(lay.tsweeps) + nxt, nvt, vt_max, s);
     return e;
   }
 
