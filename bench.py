@@ -342,12 +342,12 @@ def main():
 
     value = sweeps * cells * args.steps / elapsed
     # the dominant kernel: the sweep timing class with the largest share of
-    # the step (at 48^3 x 48^3 the 128-pencil strided tiles: x2, x3 and both
+    # the step (at 48^3 x 48^3 the 256-pencil strided tiles: x2, x3 and both
     # v1 half-steps; the x1 sweep, which also sums the velocity moment, and
     # the two-axis v2/v3 pass of each kick are timed in classes of their
     # own); each class is one kernel instantiation moving 2 * es bytes per
     # cell per launch
-    sweep_classes = ("sweep_strided_w128", "sweep_contiguous", "sweep_strided_other",
+    sweep_classes = ("sweep_strided_wide", "sweep_contiguous", "sweep_strided_other",
                      "sweep_x1_moment", "kick_plane")
     dom_name = max(sweep_classes, key=lambda k: tim[k]["total_ms"])
     dom = tim[dom_name]

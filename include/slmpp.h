@@ -137,7 +137,7 @@ typedef struct {
 
 /* Per-kernel-class timing gathered with HIP events on the context stream. */
 #define SLMPP_TIMING_CLASSES 8 /* 0: sweeps along a strided axis, tiles of
-                                     128 pencils,
+                                     128 or 256 pencils,
                                   1: sweeps along the contiguous axis,
                                   2: velocity moment, 3: Poisson + force,
                                   4: sweeps along a strided axis, other tiles,

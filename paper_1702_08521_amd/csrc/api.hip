@@ -357,7 +357,7 @@ struct slmpp_ctx {
                              fuse_moment && !rk && a == 0);
     if (p.lds_bytes > 160 * 1024)
       return fail(SLMPP_ERR_SHAPE, "pencil of %d cells does not fit the LDS tile", s.n);
-    if (fuse_moment && !rk && a == 0 && p.fast && (p.W == 64 || p.W == 128) && inner > 1 &&
+    if (fuse_moment && !rk && a == 0 && p.fast && p.W >= 64 && inner > 1 &&
         nvs % p.W == 0 && p.tiles * (int64_t)s.n <= lay.mom_doubles) {
       s.mom = mom();
       mom_w = p.W;
@@ -368,7 +368,7 @@ struct slmpp_ctx {
     hipError_t e = tic(5, 0.0, 0.0);
     if (e == hipSuccess) e = launch_pencil_table(d.storage, d.order, s, table(), tcount, stream);
     if (e == hipSuccess) e = toc();
-    const int cls = inner == 1 ? 1 : (s.mom ? 6 : (p.W == 128 ? 0 : 4));
+    const int cls = inner == 1 ? 1 : (s.mom ? 6 : (p.W >= 128 ? 0 : 4));
     if (!rk) {
       if (e == hipSuccess) e = tic(cls, 2.0 * cells * esize(), cells);
       if (e == hipSuccess) e = launch_sweep(d.storage, d.order, d.limiter, s, p, table(), stream);

@@ -465,7 +465,7 @@ struct slmpp_batch {
         // also leaves the row sums of the velocity moment
         const SweepPlan& fp = fplan[r0];
         const bool x1 = !slots[si].vel && slots[si].l == 0;
-        if (x1 && (fp.W == 64 || fp.W == 128) && fg.a.inner > 1 && g[r0].nvs % fp.W == 0) {
+        if (x1 && fp.W >= 64 && fg.a.inner > 1 && g[r0].nvs % fp.W == 0) {
           fg.a.mom = mom_next;
           for (size_t k = 0; k < rs.size(); ++k) {
             const int r = rs[k];

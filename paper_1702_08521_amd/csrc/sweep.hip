@@ -378,6 +378,33 @@ __device__ __forceinline__ void emit_vec(const SweepArgs& a, T* f, int64_t off, 
   T* dst = a.fout ? reinterpret_cast<T*>(a.fout) : f;
   __builtin_nontemporal_store(v, reinterpret_cast<V*>(dst + off));
 }
+// f as global memory: global (not flat) loads and stores of the fast
+// kernel, whose address may then keep a wave-uniform base in scalar
+// registers
+template <typename V>
+using GlobalPtr = __attribute__((address_space(1))) V*;
+template <typename V>
+__device__ __forceinline__ V global_load_nt(const V* p) {
+  return __builtin_nontemporal_load((GlobalPtr<const V>)p);
+}
+template <typename V>
+__device__ __forceinline__ void global_store_nt(V v, V* p) {
+  __builtin_nontemporal_store(v, (GlobalPtr<V>)p);
+}
+// emit_vec for the vector `lane` of a row at the wave-uniform element
+// offset uoff
+template <typename T, typename V>
+__device__ __forceinline__ void emit_vec_row(const SweepArgs& a, T* f, int64_t uoff, int lane, V v) {
+  constexpr int VN = sizeof(V) / sizeof(T);
+  if (a.fblend) {
+    const T cb = (T)a.cb, cf = (T)a.cf;
+    const V b = global_load_nt(reinterpret_cast<const V*>(reinterpret_cast<const T*>(a.fblend) + uoff) + lane);
+#pragma unroll
+    for (int c = 0; c < VN; ++c) v[c] = vfma(cb, b[c], cf * v[c]);
+  }
+  T* dst = a.fout ? reinterpret_cast<T*>(a.fout) : f;
+  global_store_nt(v, reinterpret_cast<V*>(dst + uoff) + lane);
+}
 template <bool STAGE = true, typename T>
 __device__ __forceinline__ void emit_one(const SweepArgs& a, T* f, int64_t off, T v) {
   if (!STAGE) {
@@ -708,8 +735,15 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, SweepPlan pl,
 // W divides `inner` (strided) or inner == 1 (contiguous), RC divides n,
 // VN divides RC (and n when contiguous), and all pencil / cell counts of a
 // block fit in 32 bits.
+// Strided 256-pencil tiles (48-cell FP32 pencils) run 512 threads in two
+// segments with at most 128 VGPRs, so that two workgroups share a CU: the
+// register bound costs a few spilled values per tile, and the wider rows
+// (1 KiB per row and tile) and the loads of two tiles in flight per CU
+// make these sweeps 4-14% faster than 128-pencil tiles at 48^3 x 48^3.
 template <typename T, int ORDER, int RC, int WT, bool CONTIG, bool MOM>
-__global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan pl,
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, WT == 256 ? 512 : 256),
+                               amdgpu_waves_per_eu(WT == 256 ? 4 : 1)))
+sweep_fast_kernel(SweepArgs a, SweepPlan pl,
                                                          const PencilEntry<T>* __restrict__ table) {
   extern __shared__ __align__(16) unsigned char smem[];
   using V = typename Vec<T>::type;
@@ -719,7 +753,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
   static_assert(RC % VN == 0, "segment length must be a multiple of the vector width");
   const int n = a.n, G = pl.G, P = pl.pitch;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int S = nthr / W;
+  const int S = WT == 256 ? 2 : nthr / W;
   const bool periodic = a.bc == SLMPP_BC_PERIODIC;
   const int cstride = CONTIG ? 1 : W;
   const int pstride = CONTIG ? P : 1;
@@ -735,6 +769,11 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
   int loff[NV];       // LDS element offset of vector k
   int64_t goff0;      // global element offset of vector 0 relative to the tile
   int64_t gstep;      // between consecutive vectors of the thread
+  // strided 256-pencil tiles: a row of the tile is the 64 vectors of one
+  // wavefront, so the row part of each address is wave-uniform
+  constexpr bool ROWWAVE = !CONTIG && W / VN == 64;
+  int64_t urow = 0;   // wave-uniform row offset of vector 0
+  int vlane = 0;      // vector of the lane within its row
   int vlim[NV];       // vector k exists when the tile has more than vlim[k] valid pencils
   if constexpr (CONTIG) {
 #pragma unroll
@@ -756,6 +795,10 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
     }
     goff0 = (int64_t)i0 * inner + c * VN;
     gstep = (int64_t)S * VN * inner;
+    if constexpr (ROWWAVE) {
+      urow = (int64_t)__builtin_amdgcn_readfirstlane(i0) * inner;
+      vlane = c;
+    }
   }
   // strided periodic tiles with G <= n fill their ghost rows while staging
   const bool wrap_rows = !CONTIG && periodic && G <= n;
@@ -795,6 +838,13 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
     return r;
   };
 
+  auto load_vec = [&](const T* fb, int64_t gb, int k) -> V {
+    if constexpr (ROWWAVE)
+      return global_load_nt(reinterpret_cast<const V*>(fb + (gb + urow + k * gstep)) + vlane);
+    else
+      return global_load_nt(reinterpret_cast<const V*>(fb + gb + goff0 + k * gstep));
+  };
+
   V pf[NV];
   int64_t t = blockIdx.x;
   int wv_next = 0;
@@ -808,8 +858,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (vlim[k] < wv_next)
-        pf[k] = __builtin_nontemporal_load(
-            reinterpret_cast<const V*>(f_next + gb_next + goff0 + k * gstep));
+        pf[k] = load_vec(f_next, gb_next, k);
   }
   for (; t < pl.tiles; t += gridDim.x) {
     const int wv = wv_next;
@@ -881,8 +930,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
 #pragma unroll
       for (int k = 0; k < NV; ++k)
         if (vlim[k] < wv_next)
-          pf[k] = __builtin_nontemporal_load(
-              reinterpret_cast<const V*>(f_next + gb_next + goff0 + k * gstep));
+          pf[k] = load_vec(f_next, gb_next, k);
     }
     // ---- compute ----
     const PencilEntry<T> e = ent[jj];
@@ -914,17 +962,20 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(SweepArgs a, SweepPlan 
       if (vlim[k] < wv) {
         V v;
         get(tile + loff[k], v);
-        emit_vec(a, fc, gbase + goff0 + k * gstep, v);
+        if constexpr (ROWWAVE)
+          emit_vec_row(a, fc, gbase + urow + k * gstep, vlane, v);
+        else
+          emit_vec(a, fc, gbase + goff0 + k * gstep, v);
       }
     }
     if constexpr (MOM) {
-      // fused velocity moment (strided tiles of 64 or 128 pencils within
+      // fused velocity moment (strided tiles of 64, 128 or 256 pencils within
       // one velocity block): LPR lanes per tile row each add 16 of the
       // row's pencils in double (16-byte reads, start rotated by the row so
       // the lanes of a wavefront spread over the LDS banks), then the
       // partial sums are combined in a fixed order and stored per tile and
       // row
-      static_assert(!CONTIG && (WT == 64 || WT == 128), "fused moment needs wide strided tiles");
+      static_assert(!CONTIG && (WT == 64 || WT == 128 || WT == 256), "fused moment needs wide strided tiles");
       constexpr int LPR = WT / 16;
       const int q = tid % LPR;
       for (int i = tid / LPR; i < n; i += nthr / LPR) {
@@ -1280,6 +1331,12 @@ hipError_t launch_w(const SweepArgs& a, const SweepPlan& p, const void* table, h
     if (p.fast) {
       if (a.inner == 1) return launch_fast<T, ORDER, RC, 64, true>(a, p, table, s);
       switch (p.W) {
+        case 256:
+          if constexpr (RC == 24 && ORDER == 7 && sizeof(T) == 4) {
+            if (a.mom) return launch_fast<T, ORDER, RC, 256, false, true>(a, p, table, s);
+            return launch_fast<T, ORDER, RC, 256, false>(a, p, table, s);
+          }
+          break;
         case 128:
           if (a.mom) return launch_fast<T, ORDER, RC, 128, false, true>(a, p, table, s);
           return launch_fast<T, ORDER, RC, 128, false>(a, p, table, s);
@@ -1525,6 +1582,12 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
     if (W == 0) W = 64;
   }
   while (W > 1 && lds(W, false) > 96 * 1024) W /= 2;
+  // 48-cell strided SL-MPP7 pencils take tiles of two 24-cell segments,
+  // 256 pencils wide in FP32 (see sweep_fast_kernel) and 128 in FP64 (two
+  // such workgroups fit a CU in registers and LDS, with 1 KiB per row)
+  const bool wide = !contiguous && n == 48 && order == 7 && inner % (es == 4 ? 256 : 128) == 0 &&
+                    W_override == 0 && S_override <= 0 && limiter == SLMPP_LIM_MPP;
+  if (wide) W = es == 4 ? 256 : 128;
   // R: cells per thread; a compile-time length when it divides n
   int R = 0;
   if (S_override > 0) {
@@ -1541,6 +1604,10 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
     p.S = R ? n / R : std::max(1, std::min(256 / std::max(1, W), std::max(1, n / 8)));
   }
   p.S = std::max(1, std::min(p.S, 256 / std::max(1, W)));
+  if (wide) {
+    R = 24;
+    p.S = 2;
+  }
   if (R && p.S * R != n) R = 0;
   if (limiter != SLMPP_LIM_MPP) R = 0;  // compile-time segments exist for SL-MPP only
   p.R = R;
@@ -1555,7 +1622,7 @@ SweepPlan plan_sweep(int dtype, int order, int limiter, int32_t n, int64_t npen,
                       (int64_t)n * W < ((int64_t)1 << 24);
   p.fast = R > 0 && R % vn == 0 && fits32 && W_override == 0 &&
            (contiguous ? (W == 64 && n % vn == 0) : (inner % W == 0 && inner % vn == 0 &&
-                                                     (W == 128 || W == 64 || W == 48 || W == 32)));
+                                                     (W == 256 || W == 128 || W == 64 || W == 48 || W == 32)));
   if (R == 32 && !p.fast) {  // 32-cell segments exist in the fast kernel only
     R = 0;
     p.R = 0;

@@ -25,7 +25,7 @@ FLAG_MERGE_KICKS = 2
 FLAG_ISOLATED = 4
 FLAG_SEPARATE_KICKS = 8
 TIMING_CLASSES = 8
-TIMING_NAMES = ("sweep_strided_w128", "sweep_contiguous", "moment", "poisson",
+TIMING_NAMES = ("sweep_strided_wide", "sweep_contiguous", "moment", "poisson",
                 "sweep_strided_other", "pencil_table", "sweep_x1_moment", "kick_plane")
 
 
