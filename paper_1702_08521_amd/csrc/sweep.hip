@@ -117,11 +117,23 @@ __device__ __forceinline__ T minmod4(T a, T b, T c, T d) {
   return med3(minmod2(a, b), minmod2(c, d), T(0));
 }
 
+// 2 |zeta| phib as one rounded product (never fused into a later add)
 template <typename T>
-__device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T u_plus, T u_minus) {
+__device__ __forceinline__ T pp_product(T tz, T phib) {
+#pragma clang fp contract(off)
+  return tz * phib;
+}
+
+template <typename T>
+__device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T p) {
   // theta = U^UP / (U^UP - U) on each side whose half-update is negative
   // (zero when the denominator is not positive), clamped to [0, 1]; the
   // flux moves toward the upwind value f0 by 1 - min(theta+, theta-).
+  // p = 2 |zeta| phib (rounded); the half-updates and the limited flux are
+  // formed without contraction, each operation rounded once.
+#pragma clang fp contract(off)
+  const T u_plus = f0 - p;
+  const T u_minus = fp1 + p;
   T th = T(1);
   if (u_plus < T(0)) {
     const T up = f0 - tz * f0;
@@ -129,7 +141,7 @@ __device__ __noinline__ T pp_limit(T phib, T f0, T fp1, T tz, T u_plus, T u_minu
     th = den > T(0) ? vmin(vmax(up / den, T(0)), T(1)) : T(0);
   }
   if (u_minus < T(0)) {
-    const T up = vfma(tz, f0, fp1);
+    const T up = fp1 + tz * f0;
     const T den = up - u_minus;
     th = vmin(th, den > T(0) ? vmin(vmax(up / den, T(0)), T(1)) : T(0));
   }
@@ -194,10 +206,11 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha) {
       phib = accept ? phi : c;
     }
     if constexpr (LIM == SLMPP_LIM_MPP) {
-      // PP limiter, Sec. 2.1.1: keep both half-updates non-negative
-      const T u_plus = vfma(-tz, phib, f0);
-      const T u_minus = vfma(tz, phib, fp1);
-      if (vmin(u_plus, u_minus) < T(0)) phib = pp_limit(phib, f0, fp1, tz, u_plus, u_minus);
+      // PP limiter, Sec. 2.1.1: keep both half-updates U+ = f_i - p and
+      // U- = f_{i+1} + p (p = 2 |zeta| phib, rounded once) non-negative.
+      // For floats a - b < 0 exactly when a < b, so the test needs only p.
+      const T p = pp_product(tz, phib);
+      if (p > f0 || -p > fp1) phib = pp_limit(phib, f0, fp1, tz, p);
     }
     return phib;
   }
