@@ -3,6 +3,7 @@
 // workgroup working in LDS (Sec. 2.2, App. C).  Double precision.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -164,8 +165,11 @@ __device__ void lds_dft(const double2* in, double2* out, const double2* tw, int 
 
 // One workgroup per run: rho -> phi_hat = G rho_hat -> phi -> accel.
 // LDS: two complex work arrays, then per axis the roots of unity and the
-// Laplacian symbol sym_l(k) / h_l^2 (see poisson_lds).
-__global__ void __launch_bounds__(256) batch_poisson_kernel(const BatchRun* __restrict__ runs) {
+// Laplacian symbol sym_l(k) / h_l^2 (see poisson_lds).  Up to one thread
+// per spatial cell of the largest run (at most 1024): each DFT output is a
+// serial chain of LDS reads, so the chains are spread over as many
+// wavefronts as there are outputs.
+__global__ void __launch_bounds__(1024) batch_poisson_kernel(const BatchRun* __restrict__ runs) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BatchRun& r = runs[blockIdx.x];
   const int D = r.D;
@@ -316,7 +320,8 @@ hipError_t prepare_batch_kernels(int dtype, size_t sweep_lds, int max_nxs) {
 hipError_t launch_batch_poisson(const BatchRun* runs, int nruns, int max_nxs, hipStream_t s) {
   if (nruns <= 0) return hipSuccess;
   const size_t lds = poisson_lds(max_nxs);
-  hipLaunchKernelGGL(batch_poisson_kernel, dim3(nruns), dim3(256), lds, s, runs);
+  const int threads = std::min(1024, std::max(64, (max_nxs + 63) / 64 * 64));
+  hipLaunchKernelGGL(batch_poisson_kernel, dim3(nruns), dim3(threads), lds, s, runs);
   return hipGetLastError();
 }
 

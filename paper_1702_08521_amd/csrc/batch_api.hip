@@ -124,7 +124,9 @@ Layout layout_of(const std::vector<slmpp_grid_desc>& d) {
       L.max_items += (a >= g.D ? kicks : 1) * ((npen + kMinW - 1) / kMinW);
     }
     L.nmitems += g.nxs;
-    L.mom_doubles += g.ncell / 64 + 1;  // row sums of a fused x_1 sweep (tiles of >= 64 pencils)
+    // row sums of a fused x_1 sweep: tiles of >= 64 pencils, or chunks of
+    // 8 velocity cells for 1D1V runs in the tile launch
+    L.mom_doubles += g.ncell / (g.D == 1 ? 8 : 64) + 1;
     max_cells = std::max(max_cells, g.ncell);
     stage = std::max(stage, g.nxs + sumnv);
   }
@@ -525,6 +527,24 @@ struct slmpp_batch {
         b.table = table_of(r, slots[si]);
         b.order = d[r].order;
         b.count = (int32_t)count;
+        // the x_1 sweep of a 1D1V run leaves the velocity moment's row sums
+        // in chunks of 8 velocity cells (the same for every tile width)
+        if (!slots[si].vel && slots[si].l == 0 && g[r].D == 1 && p.W % 8 == 0 &&
+            g[r].nvs % 8 == 0) {
+          b.a.mom = mom_next;
+          BatchReduce br{};
+          br.part = mom_next;
+          br.rho = at<double>(lay.rho[r]);
+          br.n = a.n;
+          br.ncol = 1;
+          br.nsub = g[r].nvs / 8;
+          br.dvol = runs[r].dvol;
+          reduce.push_back(br);
+          mom_fused[r] = 1;
+          rowsums[r] = g[r].ncell / 8;
+          max_reduce_cells = std::max(max_reduce_cells, g[r].nxs);
+          mom_next += g[r].ncell / 8;
+        }
         const int sidx = (int)sweeps.size();
         sweeps.push_back(b);
         for (int64_t t = 0; t < p.tiles; ++t) items.push_back(BatchItem{sidx, 0, t});

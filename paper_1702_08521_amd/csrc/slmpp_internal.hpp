@@ -39,7 +39,7 @@ struct SweepArgs {
   int32_t rk;           // 1: a TVD-RK stage (interface values at zero Courant
                         //    number, update with nu = c dt / h, no shift)
   double* mom;          // non-null: per-tile sums of the result over each tile row
-                        // (fast strided 64-pencil tiles only), mom[tile * n + i]
+                        // (strided tiles within one velocity block), mom[tile * n + i]
   // several runs of one geometry in one fast launch (batched ensembles):
   // tile t belongs to run t / tpr, whose f and pencil table are fmulti[r]
   // and tmulti[r] (null: the single run f, table)

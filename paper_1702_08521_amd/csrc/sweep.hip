@@ -671,6 +671,26 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const SweepPlan& 
   __syncthreads();
   const T* res = RC > 0 ? tile : tout;  // same geometry as the tile
 
+  // ---- fused velocity moment (batched 1D1V x_1 sweeps: the pencils of a
+  // tile are consecutive velocity cells): each lane adds 8 consecutive
+  // results of a tile row in double and stores that chunk sum at
+  // mom[(p0 / 8 + chunk) n + i]; chunks of 8 for every tile width, so the
+  // moment does not depend on W (W and the number of velocity cells are
+  // multiples of 8 here, hence so is wv)
+  if (!contiguous && a.mom != nullptr) {
+    const int CPR = W / 8;
+    const int q = tid % CPR;
+    if (8 * q < wv) {
+      for (int i = tid / CPR; i < n; i += nthr / CPR) {
+        const T* row = res + (i + G) * W + 8 * q;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v += (double)row[k];
+        a.mom[(p0 / 8 + q) * n + i] = v;
+      }
+    }
+  }
+
   // ---- stream the tile out in place ---------------------------------------
   if (contiguous) {
     const int total = wv * n;

@@ -297,8 +297,9 @@ def test_batch_ensemble_shaped_2d2v_members(S, storage):
     two runs per order, plus one 1D1V run.  With every eligible sweep
     grouped, the x_1 sweeps take the persistent kernel's 128-pencil tiles of
     16 cells with the fused moment and the kicks the two-axis pass over the
-    64^2 planes, at both orders; with none grouped, the tile launch.  Both
-    against the oracle for three steps."""
+    64^2 planes, at both orders; with none grouped, the tile launch (its
+    x_1 tiles leave the moment's row sums too).  Both against the oracle
+    for three steps."""
     specs = []
     for order in (5, 7):
         for k, a in ((0.35, 0.05), (0.55, 0.3)):

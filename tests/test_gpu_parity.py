@@ -221,6 +221,35 @@ def test_small_3d3v_steps(S, storage):
         assert err <= (1e-12 if storage == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_2d2v_32x64_steps(S, order, storage):
+    """2D2V at 32^2 x 64^2 (the ensemble's 2D2V member grid) through one
+    context, SL-MPP5 and SL-MPP7: the x_2 and x_1 sweeps run strided 32-cell
+    pencils (128-pencil tiles of two 16-cell segments, the x_1 sweep with
+    the moment's row sums), the kicks the two-axis pass over 64^2 planes.
+    Five steps against the oracle."""
+    spec = W.landau_run(2, 32, 64, 0.5, 0.2, order)
+    say(f"case 2d2v 32x64 order={order} storage={storage}")
+    ctx = _ctx(S, spec, storage)
+    ctx.timing_enable(True)
+    ctx.step(spec["dt"], 5)
+    tim = ctx.timing_read()
+    got = ctx.get_f()
+    ctx.close()
+    f0 = None
+    if storage == 1:
+        s, gv = W.separable_factors(spec)
+        f0 = _stored(O.init_separable(O.make_grid(spec), s, gv), 1)
+    run = O.Run(spec, f0)
+    run.step(spec["dt"], 5)
+    err = l1rel(got, run.f)
+    say(f"  L1 rel = {err:.3e}; classes {sorted(k for k, v in tim.items() if v['launches'])}")
+    assert tim["kick_plane"]["launches"] == 10
+    assert tim["sweep_x1_moment"]["launches"] == 5
+    assert err <= (1e-12 if storage == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("which", ["landau_1d1v", "2d2v_16x16", "2d2v_48_f32", "2d2v_48_f64"])
 def test_fused_moment_field_matches_oracle(S, which):
     """The step takes the velocity moment from row sums left by the x_1 sweep
