@@ -1056,7 +1056,9 @@ constexpr int kPlaneFast = 4;  // integer shifts read directly in the plane kern
 
 template <typename T, int ORDER, int N>
 struct PlaneShape {
-  static constexpr int R = N == 64 ? 16 : (N == 48 ? 12 : 8);  // cells per thread
+  // cells per thread (FP32 64^2 planes: 512 threads of 8 cells, whose extra
+  // waves outweigh the segment-boundary faces they add)
+  static constexpr int R = N == 64 ? (sizeof(T) == 4 ? 8 : 16) : (N == 48 ? 12 : 8);
   static constexpr int S = N / R;                               // segments per pencil
   static constexpr int PB = sizeof(T) == 4 ? (N == 24 ? 3 : N == 32 ? 2 : 1) : (N == 24 ? 2 : 1);
   static constexpr int threads = PB * N * S;
