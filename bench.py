@@ -126,10 +126,11 @@ def cpu_baseline(spec_fn, n_nproc, n_one, repeats=5):
         # a Strang step sweeps every x axis once and every v axis twice
         weights = {k: (1 if k[0] == "x" else 2) for k in per_axis}
         t_step = sum(w / per_axis[k] for k, w in weights.items())
-        legs[threads] = {"grid": f"{n}^{D} x {n}^{D}", "cells": cells,
+        legs[threads] = {"grid": " x ".join(str(v) for v in list(s["nx"][:D]) + list(s["nv"][:D])),
+                         "cells": cells,
                          "cell_updates_per_s": sum(weights.values()) / t_step,
                          "per_axis": {k: round(v, 1) for k, v in per_axis.items()}}
-        log(f"[bench] cpu baseline {threads} thread(s) at {n}^{D}x{n}^{D}: "
+        log(f"[bench] cpu baseline {threads} thread(s) at {legs[threads]['grid']}: "
             f"{legs[threads]['cell_updates_per_s']:.3e} cell-updates/s per sweep")
     wall = time.perf_counter() - t_all
     return {
@@ -140,8 +141,8 @@ def cpu_baseline(spec_fn, n_nproc, n_one, repeats=5):
         "sample": (f"FP64 oracle, gcc -O3 -march=native -ffp-contract=off, OpenMP over pencils, on "
                    f"{cpu_model()} ({os.cpu_count()} CPUs, {nproc} threads used); median of "
                    f"{repeats} timed sweeps after one warm-up, every axis, weighted as in a "
-                   f"Strang step (x once, v twice): {nproc} threads at {n_nproc}^6, 1 thread at "
-                   f"{n_one}^6 (per cell, the cost being linear in cells); {wall:.1f} s"),
+                   f"Strang step (x once, v twice): {nproc} threads at {legs[nproc]['grid']}, 1 thread "
+                   f"at {legs[1]['grid']} (per cell, the cost being linear in cells); {wall:.1f} s"),
         "single_thread": {"value": legs[1]["cell_updates_per_s"], "cores": 1,
                           "grid": legs[1]["grid"], "per_axis": legs[1]["per_axis"]},
         "per_axis": legs[nproc]["per_axis"],
@@ -608,6 +609,7 @@ def ensemble_cpu_baseline(specs, steps):
 
     import oracle as O
 
+    O.use_native()
     runs = [O.Run(s) for s in specs]
     t0 = time.perf_counter()
     for run, s in zip(runs, specs):
@@ -615,9 +617,11 @@ def ensemble_cpu_baseline(specs, steps):
     dt = time.perf_counter() - t0
     upd = steps * sum(int(np.prod(s["nx"][:s["D"]])) * int(np.prod(s["nv"][:s["D"]])) * 3 * s["D"]
                       for s in specs)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     return {"value": upd / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} Strang steps of all {len(specs)} ensemble runs, FP64, {dt:.2f} s"}
+            "sample": (f"{steps} Strang steps of all {len(specs)} ensemble runs, FP64 oracle, gcc -O3 "
+                       f"-march=native -ffp-contract=off, OpenMP over pencils, on {cpu_model()} "
+                       f"({threads} threads), {dt:.2f} s")}
 
 
 if __name__ == "__main__":
