@@ -1135,8 +1135,17 @@ __global__ void __launch_bounds__((PlaneShape<T, ORDER, N>::threads))
     }
   }
   // compute map (segment-major): plane cq, pencil cj, cells m0 .. m0 + R - 1
-  const int s = tid / PN;
-  const int u = tid - s * PN;
+  // of segment s.  With four segments and a wavefront holding parts of two,
+  // the segments are laid out in the order 2, 0, 1, 3, so that wavefronts
+  // pair segments whose early MP accept fails at the same processing
+  // positions for a profile with its extremum at the pencil's centre and
+  // zero ghost cells at both ends: the first faces of the inflow segment
+  // and of the segment starting at the centre, the last faces of the other
+  // two.  Which lane computes which (segment, pencil) does not change any
+  // result.
+  const int sl = tid / PN;
+  const int s = S == 4 ? (0x3102 >> (4 * sl)) & 15 : sl;
+  const int u = tid - sl * PN;
   const int cq = u / N;
   const int cj = u - cq * N;
   const int m0 = s * R;
