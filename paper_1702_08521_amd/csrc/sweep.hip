@@ -1136,15 +1136,16 @@ __global__ void __launch_bounds__((PlaneShape<T, ORDER, N>::threads))
   }
   // compute map (segment-major): plane cq, pencil cj, cells m0 .. m0 + R - 1
   // of segment s.  With four segments and a wavefront holding parts of two,
-  // the segments are laid out in the order 2, 0, 1, 3, so that wavefronts
-  // pair segments whose early MP accept fails at the same processing
-  // positions for a profile with its extremum at the pencil's centre and
-  // zero ghost cells at both ends: the first faces of the inflow segment
-  // and of the segment starting at the centre, the last faces of the other
-  // two.  Which lane computes which (segment, pencil) does not change any
-  // result.
+  // the segments are laid out in the order 2, 0, 3, 1 (wavefronts hold
+  // segments 2 and 0, 0 and 3, 3 and 1), so that a wavefront's lanes fail
+  // the early MP accept at few distinct processing positions for a profile
+  // with its extremum at the pencil's centre and zero ghost cells at both
+  // ends: segment 2 (starting at the centre) fails at its first two faces,
+  // segment 0 (inflow) at its first, segment 1 (ending at the centre) at its
+  // last, segment 3 (outflow) rarely.  Which lane computes which
+  // (segment, pencil) does not change any result.
   const int sl = tid / PN;
-  const int s = S == 4 ? (0x3102 >> (4 * sl)) & 15 : sl;
+  const int s = S == 4 ? (0x1302 >> (4 * sl)) & 15 : sl;
   const int u = tid - sl * PN;
   const int cq = u / N;
   const int cj = u - cq * N;
