@@ -185,13 +185,17 @@ __device__ __forceinline__ T face_flux(const T* q, const T* w, T tz, T alpha) {
   } else {
     const T fm2 = q[o], fm1 = q[o + 1], f0 = q[o + 2], fp1 = q[o + 3], fp2 = q[o + 4];
     const T dl = f0 - fm1, dr = fp1 - f0;
-    // App. A steps 2-3.  The flux is kept when it lies between f_i and f*:
-    // that closed interval always lies within [f^min, f^max] of steps 4-6
-    // (f* is f_i, f_{i+1} <= f^UL or f^UL, each inside both bounds), so
-    // step 7 would return the flux unchanged there.  The strict test of the
-    // text only sends the end points (a flux equal to f_i, as in regions of
-    // zeros) through steps 4-7.
-    const T fstar = f0 + minmod2(dr, alpha * dl);
+    // App. A steps 2-3.  f* = f_i + minmod(f_{i+1} - f_i, alpha (f_i - f_{i-1}))
+    // is the median of f_{i+1}, f^UL = f_i + alpha (f_i - f_{i-1}) and f_i
+    // (adding f_i commutes with the median); it is formed that way, from
+    // the same rounded f^UL that the bounds of step 6 use.  The flux is kept
+    // when it lies between f_i and f*: f_i, f_{i+1} and f^UL each lie within
+    // [f^min, f^max] (each bound is a min or max over sets holding f_i and
+    // f_{i+1} or f_i and f^UL), so does every value between two of them, and
+    // step 7 returns the flux unchanged there, in floating point as well.
+    // The strict test of the text only sends the end points (a flux equal
+    // to f_i, as in regions of zeros) through steps 4-7.
+    const T fstar = med3(fp1, vfma(alpha, dl, f0), f0);
     const bool accept = med3(phi, f0, fstar) == phi;
     T phib = phi;
     // steps 4-7, skipped when every lane of the wavefront accepted (the
