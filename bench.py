@@ -338,6 +338,18 @@ def main():
     elapsed = time.perf_counter() - t0
     tim = ctx.timing_read()
     ctx.timing_enable(False)
+    no_events_ms = None
+    if cells < (1 << 24):
+        # small grids are bound by launch latency, where the per-launch
+        # events of the timed region above add a large share: the same
+        # number of further steps with only two events around them
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step(dt, args.steps)
+        e1.record(stream)
+        e1.synchronize()
+        no_events_ms = e0.elapsed_time(e1) / args.steps
     diag = ctx.diag()
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; diag {diag}")
 
@@ -406,6 +418,10 @@ def main():
         "detail": {"per_class": per_class, "mass": diag["mass"], "f_min": diag["f_min"],
                    "nonfinite": diag["nonfinite"]},
     }
+    if no_events_ms is not None:
+        out["detail"]["without_launch_events"] = {
+            "steps": args.steps, "ms_per_step": no_events_ms,
+            "cell_updates_per_s": sweeps * cells / (no_events_ms * 1e-3)}
     # velocity-space diagnostics of the same f (each one read of f)
     nxs = int(np.prod(spec["nx"][:D]))
     nvs = int(np.prod(spec["nv"][:D]))
