@@ -71,6 +71,27 @@ def read_traffic(kernel_key):
     return ent.get("bytes_per_launch")
 
 
+def alloc_f(S, torch, shape, tdt, dev):
+    """f in physically contiguous device memory (slmpp_alloc_device: the
+    strided sweeps take fewer address translations), or a torch allocation
+    where the driver cannot provide such memory.  Returns (buffer or None,
+    tensor, placement)."""
+    import numpy as np
+
+    nbytes = int(np.prod(shape)) * torch.empty((), dtype=tdt).element_size()
+    try:
+        buf = S.DeviceBuffer(nbytes, contiguous=True)
+    except S.SlmppError:
+        return None, torch.empty(shape, dtype=tdt, device=dev), "default"
+    return buf, buf.tensor(shape, tdt, dev), "contiguous"
+
+
+def release_f(torch, buf):
+    torch.cuda.synchronize()
+    if buf is not None:
+        buf.free()
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -318,7 +339,10 @@ def main():
     log(f"[bench] {spec['name']} cells={cells:.3e} dtype={args.dtype} steps={args.steps} warmup={args.warmup}")
 
     stream = torch.cuda.Stream(device=dev)
-    ctx = slmpp.Context(slmpp.make_desc(spec, storage), stream=stream, device=dev)
+    fshape = tuple(spec["nx"][:D]) + tuple(spec["nv"][:D])
+    tdt = torch.float32 if storage == slmpp.F32 else torch.float64
+    f_buf, f_t, placement = alloc_f(slmpp, torch, fshape, tdt, dev)
+    ctx = slmpp.Context(slmpp.make_desc(spec, storage), f=f_t, stream=stream, device=dev)
     s, gv = W.separable_factors(spec)
     ctx.init_f_separable(s, gv)
     ctx.field()
@@ -399,6 +423,7 @@ def main():
             "cells": cells,
             "sweeps_per_step": sweeps,
             "dt": dt,
+            "f_placement": placement,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -453,7 +478,8 @@ def main():
         # the same workload from the same start with FP64 storage on the same
         # GPU: its rate, and the error of FP32 storage after the same steps
         total = args.warmup + args.steps
-        ctx64 = slmpp.Context(slmpp.make_desc(spec, slmpp.F64), stream=stream, device=dev)
+        f64_buf, f64_t, _ = alloc_f(slmpp, torch, fshape, torch.float64, dev)
+        ctx64 = slmpp.Context(slmpp.make_desc(spec, slmpp.F64), f=f64_t, stream=stream, device=dev)
         ctx64.init_f_separable(s, gv)
         ctx64.field()
         d64_0 = ctx64.diag()
@@ -494,9 +520,11 @@ def main():
         log(f"[bench] fp32 vs fp64 after {total} steps: {out['detail']['fp32_vs_fp64']}")
         del a32, a64
         ctx64.close()
-        del ctx64
+        del ctx64, f64_t
+        release_f(torch, f64_buf)
     ctx.close()
-    del ctx
+    del ctx, f_t
+    release_f(torch, f_buf)
     torch.cuda.empty_cache()
 
     if args.merge_compare > 0:

@@ -294,6 +294,22 @@ slmpp_status slmpp_timing_read(slmpp_ctx* ctx, slmpp_timing* out);
 slmpp_status slmpp_copy_device(void* dst_dev, const void* src_dev, size_t bytes,
                                void* hip_stream);
 
+/* Device memory for f (or any caller buffer) on the current device, for
+ * callers that want to choose its placement.  contiguous = 1 asks the
+ * driver for physically contiguous memory (hipExtMallocWithFlags with
+ * hipDeviceMallocContiguous): the strided sweeps then need fewer address
+ * translations (measured 1-2% faster per sweep at 48^3 x 48^3 than the
+ * same sweep over an ordinary allocation in the same process);
+ * contiguous = 0 is a plain hipMalloc.  The caller owns the memory and
+ * releases it with slmpp_free_device once no work on it is pending.
+ * Errors (*out is set to NULL first, when out is not NULL, and nothing is
+ * allocated): out NULL or bytes 0 (SLMPP_ERR_INVALID); the driver cannot
+ * provide the memory (SLMPP_ERR_DEVICE).  The contents are undefined. */
+slmpp_status slmpp_alloc_device(size_t bytes, int32_t contiguous, void** out);
+
+/* Release memory from slmpp_alloc_device (NULL is accepted and ignored). */
+slmpp_status slmpp_free_device(void* p);
+
 /* ------------------------------------------------------------------------
  * Batched ensembles: many independent runs (each with its own grid, order,
  * dt and initial condition) advanced together.  Every phase of the Strang

@@ -1099,4 +1099,33 @@ slmpp_status slmpp_copy_device(void* dst_dev, const void* src_dev, size_t bytes,
   return SLMPP_OK;
 }
 
+slmpp_status slmpp_alloc_device(size_t bytes, int32_t contiguous, void** out) {
+  if (out) *out = nullptr;
+  if (!out || bytes == 0) {
+    g_error = "alloc_device: out is NULL or bytes is 0";
+    return SLMPP_ERR_INVALID;
+  }
+  void* p = nullptr;
+  const hipError_t e = contiguous ? hipExtMallocWithFlags(&p, bytes, hipDeviceMallocContiguous)
+                                  : hipMalloc(&p, bytes);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();  // the failed allocation's error is reported here, not by the next call
+    g_error = std::string("alloc_device: ") + std::to_string(bytes) + " bytes" +
+              (contiguous ? " of contiguous memory" : "") + ": " + hipGetErrorString(e);
+    return SLMPP_ERR_DEVICE;
+  }
+  *out = p;
+  return SLMPP_OK;
+}
+
+slmpp_status slmpp_free_device(void* p) {
+  if (!p) return SLMPP_OK;
+  const hipError_t e = hipFree(p);
+  if (e != hipSuccess) {
+    g_error = std::string("free_device: ") + hipGetErrorString(e);
+    return SLMPP_ERR_DEVICE;
+  }
+  return SLMPP_OK;
+}
+
 }  // extern "C"

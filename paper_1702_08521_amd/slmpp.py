@@ -111,6 +111,8 @@ SIGNATURES = {
     "slmpp_timing_enable": (_S, [_VP, _I32]),
     "slmpp_timing_read": (_S, [_VP, ctypes.POINTER(Timing)]),
     "slmpp_copy_device": (_S, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "slmpp_alloc_device": (_S, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_VP)]),
+    "slmpp_free_device": (_S, [_VP]),
     "slmpp_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GridDesc), _I32]),
     "slmpp_batch_create": (_S, [ctypes.POINTER(GridDesc), ctypes.POINTER(_D), _I32,
                                 ctypes.POINTER(_VP), _VP, ctypes.c_size_t, _VP,
@@ -351,6 +353,49 @@ def advect_v_noalloc(desc: GridDesc, f, dim, dt, accel, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream(f.device)
     _check(lib().slmpp_advect_v_noalloc(ctypes.byref(desc), _VP(f.data_ptr()), int(dim), float(dt),
                                         _VP(accel.data_ptr()), _VP(s.cuda_stream)))
+
+
+class DeviceBuffer:
+    """Device memory from slmpp_alloc_device (contiguous: physically
+    contiguous placement, raising SlmppError when the driver cannot provide
+    it); tensor() views it as a torch tensor.  The buffer must outlive its
+    views and any work on them; free() (or garbage collection) releases it."""
+
+    def __init__(self, nbytes, contiguous=True):
+        p = _VP()
+        st = lib().slmpp_alloc_device(int(nbytes), 1 if contiguous else 0, ctypes.byref(p))
+        if st != OK:
+            raise SlmppError(st, (lib().slmpp_last_error(None) or b"").decode())
+        self.ptr = p.value
+        self.nbytes = int(nbytes)
+
+    def tensor(self, shape, dtype, device=None):
+        import torch
+
+        n = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+        if n > self.nbytes:
+            raise SlmppError(ERR_SHAPE, "view of %d bytes exceeds the buffer's %d" % (n, self.nbytes))
+        typestr = {torch.float32: "<f4", torch.float64: "<f8"}[dtype]
+
+        class _View:
+            pass
+
+        v = _View()
+        v.__cuda_array_interface__ = {"shape": tuple(int(x) for x in shape), "typestr": typestr,
+                                      "data": (self.ptr, False), "version": 2}
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        return torch.as_tensor(v, device=dev)
+
+    def free(self):
+        if self.ptr:
+            lib().slmpp_free_device(_VP(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def copy_device(dst_ptr, src_ptr, nbytes, stream=None):

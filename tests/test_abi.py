@@ -226,3 +226,14 @@ def test_advect_v_noalloc_rejects_before_touching_the_device():
     st = L.slmpp_advect_v_noalloc(ctypes.byref(big), fake, 0, 0.1, fake, None)
     assert st == slmpp.ERR_SHAPE
     assert b"scratch" in L.slmpp_last_error(None)
+
+
+def test_alloc_device_rejects_before_touching_the_device():
+    """slmpp_alloc_device checks its arguments before any device call."""
+    L = slmpp.lib()
+    p = ctypes.c_void_p(1234)
+    assert L.slmpp_alloc_device(0, 1, ctypes.byref(p)) == slmpp.ERR_INVALID
+    assert p.value is None  # *out cleared on failure
+    assert L.slmpp_alloc_device(1 << 20, 1, None) == slmpp.ERR_INVALID
+    assert b"alloc_device" in L.slmpp_last_error(None)
+    assert L.slmpp_free_device(None) == slmpp.OK
