@@ -182,9 +182,27 @@ def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ens
     storage = slmpp.F32 if dtype == "f32" else slmpp.F64
     stream = torch.cuda.Stream()
 
+    bufs = []
+
     def make(st, merged=False):
+        # every run's f in one physically contiguous buffer (256-byte
+        # aligned views), or torch allocations where the driver cannot
+        # provide one
+        tdt = torch.float32 if st == slmpp.F32 else torch.float64
+        shapes = [tuple(s["nx"][:s["D"]]) + tuple(s["nv"][:s["D"]]) for s in specs]
+        sizes = [int(np.prod(sh)) for sh in shapes]
+        es = 4 if st == slmpp.F32 else 8
+        q = 256 // es
+        offs, total = [], 0
+        for n in sizes:
+            offs.append(total)
+            total += (n + q - 1) // q * q
+        buf, big, placement = alloc_f(slmpp, torch, (total,), tdt,
+                                      torch.device("cuda", torch.cuda.current_device()))
+        bufs.append((buf, placement))
+        fs = [big[o:o + n].view(sh) for o, n, sh in zip(offs, sizes, shapes)]
         b = slmpp.Batch([slmpp.make_desc(dict(s, merge_kicks=merged), st) for s in specs],
-                        [s["dt"] for s in specs], stream=stream)
+                        [s["dt"] for s in specs], fs=fs, stream=stream)
         for r, s in enumerate(specs):
             sx, gv = W.separable_factors(s)
             b.init_separable(r, sx, gv)
@@ -290,6 +308,9 @@ def ensemble_leg(steps, warmup, dtype="f32", compare_fp64=True, log_prefix="[ens
         b32.close()
         b64.close()
     b.close()
+    out["f_placement"] = bufs[0][1]
+    for buf, _ in bufs:
+        release_f(torch, buf)
     return out
 
 
