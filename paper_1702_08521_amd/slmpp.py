@@ -358,8 +358,10 @@ def advect_v_noalloc(desc: GridDesc, f, dim, dt, accel, stream=None):
 class DeviceBuffer:
     """Device memory from slmpp_alloc_device (contiguous: physically
     contiguous placement, raising SlmppError when the driver cannot provide
-    it); tensor() views it as a torch tensor.  The buffer must outlive its
-    views and any work on them; free() (or garbage collection) releases it."""
+    it); tensor() views it as a torch tensor, which keeps the buffer alive.
+    free() releases the memory at once (the caller makes sure that no view
+    is used afterwards and no work on it is pending); otherwise it goes when
+    the buffer and all its views are gone."""
 
     def __init__(self, nbytes, contiguous=True):
         p = _VP()
@@ -383,6 +385,7 @@ class DeviceBuffer:
         v = _View()
         v.__cuda_array_interface__ = {"shape": tuple(int(x) for x in shape), "typestr": typestr,
                                       "data": (self.ptr, False), "version": 2}
+        v.owner = self  # torch holds the interface object as long as the tensor's storage
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         return torch.as_tensor(v, device=dev)
 

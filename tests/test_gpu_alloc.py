@@ -83,3 +83,25 @@ def test_alloc_device_view_bounds(S):
     finally:
         torch.cuda.synchronize()
         buf.free()
+
+
+def test_alloc_device_view_keeps_buffer_alive(S):
+    """A tensor view holds its buffer: dropping the last other reference
+    frees nothing until the view is gone."""
+    import gc
+    import weakref
+
+    import torch
+
+    buf = S.DeviceBuffer(4096, contiguous=True)
+    t = buf.tensor((1024,), torch.float32)
+    w = weakref.ref(buf)
+    del buf
+    gc.collect()
+    assert w() is not None
+    t.fill_(2.0)
+    assert float(t.sum()) == 2048.0
+    torch.cuda.synchronize()
+    del t
+    gc.collect()
+    assert w() is None
