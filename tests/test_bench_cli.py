@@ -25,3 +25,26 @@ def test_traffic_record_is_readable():
     t = bench.read_traffic("landau_3d3v/f32")
     # None only when the sweep source changed after the counters were taken
     assert t is None or t > 0
+
+
+def test_alloc_f_falls_back_to_torch():
+    """Where the driver cannot provide contiguous memory, bench.py places f
+    in an ordinary torch allocation and says so."""
+    sys.path.insert(0, ROOT)
+    import torch
+
+    import bench
+
+    class _Err(Exception):
+        pass
+
+    class _Refusing:
+        SlmppError = _Err
+
+        class DeviceBuffer:
+            def __init__(self, nbytes, contiguous=True):
+                raise _Err("no contiguous memory")
+
+    buf, t, placement = bench.alloc_f(_Refusing, torch, (3, 5), torch.float64, torch.device("cpu"))
+    assert buf is None and placement == "default"
+    assert t.shape == (3, 5) and t.dtype == torch.float64
