@@ -1029,7 +1029,12 @@ sweep_fast_kernel(SweepArgs a, SweepPlan pl,
         if (q == 0) a.mom[t * n + i] = v;
       }
     }
-    __syncthreads();
+    // the row sums read every thread's vectors: the next tile's LDS writes
+    // wait for them.  Without them no barrier is needed here: the next
+    // tile first writes this thread's own data-movement vectors (at the
+    // offsets it has just read), ghost rows and pencil entries, none of
+    // which another thread reads before the next barrier.
+    if constexpr (MOM) __syncthreads();
   }
 }
 
@@ -1257,7 +1262,8 @@ __global__ void __launch_bounds__((PlaneShape<T, ORDER, N>::threads))
         __builtin_nontemporal_store(v, dst + tid + NT * k);
       }
     }
-    __syncthreads();
+    // no barrier before the next tile: its first LDS writes are this
+    // thread's own data-movement vectors, at the offsets it has just read
   }
 }
 
