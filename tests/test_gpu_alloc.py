@@ -105,3 +105,23 @@ def test_alloc_device_view_keeps_buffer_alive(S):
     del t
     gc.collect()
     assert w() is None
+
+
+def test_alloc_device_refusal_leaves_the_device_usable(S):
+    """An allocation the driver cannot satisfy comes back as an error and
+    leaves nothing behind: later work on the device is unaffected."""
+    import torch
+
+    with pytest.raises(S.SlmppError) as ei:
+        S.DeviceBuffer(1 << 50, contiguous=True)  # 1 PiB
+    assert ei.value.status == S.ERR_DEVICE
+    spec = W.landau_1d1v(nx=32, nv=64, amp=0.2)
+    ctx = S.Context(S.make_desc(spec, 0))
+    ctx.init_f_separable(*W.separable_factors(spec))
+    ctx.step(spec["dt"], 3)
+    got = ctx.get_f()
+    ctx.close()
+    run = O.Run(spec)
+    run.step(spec["dt"], 3)
+    assert float(np.abs(got - run.f).sum() / np.abs(run.f).sum()) <= 1e-12
+    torch.cuda.synchronize()
